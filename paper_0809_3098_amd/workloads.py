@@ -1,0 +1,21 @@
+"""Named synthetic workloads of the driven-cavity time step.
+
+Each is fully defined by its parameters: grid nodes per side ``n`` (walls
+included), Reynolds number, lid speed 1, dt = cfl * h with cfl = 0.5, Poisson
+residual tolerance, precision, and the initial vorticity recipe.
+"""
+
+WORKLOADS = {
+    "cavity64_re1e3_fp64": dict(n=64, re=1000.0, steps=200, tol=1e-10, precision="fp64",
+                                init="rest"),
+    "cavity1024_re1e4_fp64": dict(n=1024, re=1.0e4, steps=1000, tol=1e-10, precision="fp64",
+                                  init="rest"),
+    "cavity1024_re3e4_mixed": dict(n=1024, re=3.0e4, steps=1000, tol=1e-10, precision="mixed",
+                                   init="rest"),
+    "re_sweep6": dict(members=[(5000.0, 256), (10000.0, 512), (15000.0, 768),
+                               (20000.0, 1024), (25000.0, 1024), (30000.0, 1024)],
+                      steps=1000, tol=1e-10, init="rest"),
+    "cavity4096_re3e4_mixed_noise": dict(n=4096, re=3.0e4, steps=2000, tol=1e-10,
+                                         precision="mixed", init="noise",
+                                         noise_amplitude=1e-3, noise_seed=0),
+}
