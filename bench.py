@@ -1,0 +1,146 @@
+"""Throughput of the driven-lid-cavity time step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+
+A step is one SSPRK(5,4) step of the whole hot path (five stages, each with
+transport RHS + stage combination, compact-Poisson SOR solve to tolerance,
+Thom walls) on the synthetic workload: the 1024 x 1024 cavity at Re = 1e4,
+started from rest, FP64, Poisson tolerance 1e-10.  Inputs are resident in
+HBM when timing starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-steps/s at 1024² (FP64 vs mixed+refine), achieved HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SWEEP_CELL = {0: 24.0, 1: 12.0}   # FP64 / FP32 algorithmic bytes per node per sweep
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sor_traffic.json")
+
+
+def _kernel_source_hash() -> str:
+    path = os.path.join(ROOT, "paper_0809_3098_amd", "csrc", "cavity_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(workload: str):
+    """HBM bytes per sweep launch from committed PMC counters, if still valid."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_source_sha256_16") != _kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def _cpu_baseline(n, re, steps):
+    import numpy as np  # noqa: F401
+    from oracle.cavity_oracle import CavityOracle
+    cores = os.cpu_count() or 1
+    o = CavityOracle(n, re, workers=cores)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": n * n * steps / dt / 1e6, "unit": "Mcell-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{steps} steps of the {n}x{n} Re={re:g} cavity from rest; exact DST "
+                      f"Poisson per stage (scipy.fft workers={cores}), NumPy elementwise on 1 "
+                      f"thread; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cavity1024_re1e4_fp64")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--relax-launches", type=int, default=400)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the batched and "
+              f"single-cavity paths are single-GPU designs.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0809_3098_amd.cavity import CAVITY_FP64, CAVITY_MIXED, Cavity, Params
+    from paper_0809_3098_amd.workloads import WORKLOADS
+
+    wl = WORKLOADS[args.workload]
+    n, re, tol = wl["n"], wl["re"], wl["tol"]
+    prec = CAVITY_MIXED if wl["precision"] == "mixed" else CAVITY_FP64
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    cav = Cavity(Params(n=n, re=re, poisson_tol=tol, precision=prec), device="cuda:0",
+                 stream=stream)
+    if args.warmup:
+        cav.step(args.warmup, want_stats=False)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    stats = cav.step(args.steps, want_stats=True)[0] if args.steps else None
+    torch.cuda.synchronize(dev)
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / max(args.steps, 1)
+    value = n * n * args.steps / elapsed / 1e6 if args.steps else 0.0
+
+    # Dominant kernel: the temporally blocked SOR sweep.  Average launch
+    # duration from events on the kernel's stream around back-to-back launches.
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    cav.relax(2)  # warm the scratch buffers
+    ev0.record(stream)
+    done, _ = cav.relax(args.relax_launches * 2)  # sweeps; rounded to whole launches
+    ev1.record(stream)
+    ev1.synchronize()
+    relax_ms = ev0.elapsed_time(ev1)
+    sweeps_per_launch = 2 if n > 320 else 1
+    launches = done // sweeps_per_launch
+    per_launch_s = relax_ms / 1e3 / launches
+    cells = (n - 2) ** 2
+    alg_bytes = BYTES_PER_SWEEP_CELL[0] * cells * sweeps_per_launch
+    achieved = alg_bytes / per_launch_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": _traffic(args.workload),
+                "kernel": f"k_sor<double,64,64,{sweeps_per_launch}>" if n > 320 else
+                          "k_sor<double,32,32,1>",
+                "alg_bytes_per_launch": alg_bytes,
+                "avg_launch_us": round(per_launch_s * 1e6, 3)}
+    cav.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = _cpu_baseline(n, re, args.cpu_steps)
+
+    line = {
+        "metric": METRIC, "value": round(value, 4), "unit": "Mcell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == CAVITY_FP64 else "f32+f64", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "re": re, "poisson_tol": tol,
+                   "precision": wl["precision"], "init": wl["init"],
+                   "sweeps_per_step": stats["sweeps_last_step"] if stats else None,
+                   "sweeps_per_stage": stats["sweeps_last_step"] / 5 if stats else None,
+                   "floor_limited_last_step": stats["floor_limited"] if stats else None},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

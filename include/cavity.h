@@ -1,0 +1,193 @@
+/*
+ * cavity.h -- C ABI of the MI355X driven-lid-cavity time stepper.
+ *
+ * The library advances the two-dimensional incompressible Navier-Stokes
+ * equations in vorticity-stream function form on the unit square with a
+ * moving lid (N. Cardoso and P. Bicudo, "Time dependent simulation of the
+ * Driven Lid Cavity at High Reynolds Number", arXiv:0809.3098):
+ *
+ *   - Sec. 2, eqs. (vort0), (stream0), (str), (vortfinal): the model;
+ *   - Sec. 3, eq. (Lwn): central-difference right-hand side for omega;
+ *   - Sec. 3, eqs. (SSPRK54_1)-(SSPRK54_5): SSPRK(5,4) time integration;
+ *   - Sec. 3, eqs. (stream_4O), (SequationFinal): fourth-order compact
+ *     stream equation, solved by successive over-relaxation;
+ *   - Sec. 3, eq. (vel): velocities from psi;
+ *   - Sec. 3.1: psi = 0 on the walls, Thom's wall vorticity;
+ *   - Sec. 3.2: Re = |U| L / nu with L = 1, monitors RES_psi, RES_omega
+ *     (eqs. resS, resV).
+ *
+ * Every entry point returns an int status (CAVITY_OK = 0 or a negative
+ * cavity_status); no C++ exception crosses this boundary.  After a failure
+ * cavity_last_error() returns a message for the calling thread.
+ *
+ * Field layout: every field exchanged through this ABI is an n x n array of
+ * IEEE double, row-major, indexed [j][i] with i the x index (fastest) and j
+ * the y index; node (i, j) sits at (i h, j h), h = 1/(n-1); the moving lid is
+ * row j = n-1.  Field pointers are DEVICE pointers on the device that owns
+ * the handle's stream; the library never keeps them after the call returns.
+ *
+ * Streams: all work is enqueued on the hip_stream given to cavity_create
+ * (NULL = the null stream).  Calls that return host results (stats, info)
+ * synchronise that stream before returning; the others only enqueue.
+ */
+#ifndef CAVITY_H
+#define CAVITY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum cavity_status {
+  CAVITY_OK = 0,
+  CAVITY_EINVAL = -1,     /* invalid argument (message says which)            */
+  CAVITY_ENOMEM = -2,     /* workspace too small                               */
+  CAVITY_EHIP = -3,       /* a HIP runtime call failed                         */
+  CAVITY_ENOCONV = -4,    /* a Poisson solve hit poisson_max_sweeps; the step
+                             completed with the last iterate and the state stays
+                             usable                                            */
+  CAVITY_ENONFINITE = -5, /* NaN/Inf met in a residual; the handle is poisoned */
+  CAVITY_ESTATE = -6      /* handle poisoned by an earlier ENONFINITE/EHIP     */
+};
+
+/* Arithmetic of the Poisson smoother and stencil sweeps. */
+enum cavity_precision {
+  CAVITY_FP64 = 0,   /* everything in double precision (the paper's setting)   */
+  CAVITY_MIXED = 1   /* FP32 smoother sweeps and FP32 transport stencil with
+                        FP64 residual, FP64 iterative refinement of psi, FP64
+                        stage accumulation of omega and FP64 wall vorticity    */
+};
+
+/* Parameters of one cavity (Sec. 3.2: unit square, lid speed U on top). */
+typedef struct cavity_params {
+  int32_t n;                  /* nodes per side including walls, 5 <= n <= 16385   */
+  int32_t precision;          /* enum cavity_precision                            */
+  double re;                  /* Reynolds number > 0; nu = |u_lid| / re            */
+  double u_lid;               /* lid speed U (sign allowed); 0 needs dt > 0 and nu  */
+  double nu;                  /* > 0 overrides the viscosity derived from re        */
+  double dt;                  /* > 0: fixed time step; <= 0: dt = cfl * h / |u_lid|  */
+  double cfl;                 /* used when dt <= 0; <= 0 means 0.5                  */
+  double poisson_tol;         /* stop when max-norm residual of the compact stream
+                                 equation, in vorticity units, is <= this; <= 0
+                                 means 1e-10                                       */
+  int32_t poisson_max_sweeps; /* per solve; <= 0 means 200 * n                      */
+  int32_t resume;             /* 1: omega0 and psi0 (both required) are a state
+                                 saved by cavity_fields after a step and are
+                                 adopted as they are, walls included, without a
+                                 Poisson solve, so the run continues exactly      */
+  double sor_omega;           /* relaxation parameter in (0, 2); <= 0 chooses
+                                 2 / (1 + sin(pi h))                               */
+  const double* omega0;       /* nullable device n*n initial vorticity (walls are
+                                 replaced by Thom's values); NULL = fluid at rest   */
+  const double* psi0;         /* nullable device n*n warm start for the first
+                                 Poisson solve (or the saved psi when resume = 1);
+                                 its wall values are ignored (psi = 0 on walls);
+                                 NULL = zeros                                      */
+} cavity_params;
+
+/* Per-cavity results of cavity_step. */
+typedef struct cavity_stats {
+  int64_t step;               /* steps taken since create                          */
+  double t;                   /* simulated time                                    */
+  double dt;                  /* time step in use                                  */
+  double res_psi;             /* RES_psi of the last step (eq. resS), sum / n      */
+  double res_omega;           /* RES_omega of the last step (eq. resV), sum / n    */
+  double domega_inf_over_dt;  /* max |omega^{n+1} - omega^n| / dt                  */
+  double ke;                  /* 0.5 h^2 sum over interior of (u^2 + v^2)          */
+  double last_resid_inf;      /* residual max-norm at the end of the last solve    */
+  int64_t sweeps_total;       /* relaxation sweeps since create                    */
+  int64_t sweeps_last_step;   /* relaxation sweeps in the last step (5 solves)     */
+  int32_t floor_limited;      /* 1 if a solve of the last step stopped at the
+                                 rounding floor above poisson_tol                   */
+  int32_t status;             /* CAVITY_OK / CAVITY_ENOCONV for this cavity        */
+} cavity_stats;
+
+/* Result of a stand-alone Poisson solve. */
+typedef struct cavity_poisson_info {
+  int64_t sweeps;             /* relaxation sweeps performed                       */
+  double resid_inf;           /* final residual max-norm (vorticity units)        */
+  int32_t floor_limited;      /* see cavity_stats                                  */
+  int32_t status;             /* CAVITY_OK or CAVITY_ENOCONV                      */
+} cavity_poisson_info;
+
+typedef struct cavity_s* cavity_t;
+
+/*
+ * Device workspace needed for `count` cavities with parameters p[0..count-1].
+ * Writes the byte count to *bytes.  EINVAL on bad parameters.
+ */
+int cavity_workspace_bytes(const cavity_params* p, int32_t count, size_t* bytes);
+
+/*
+ * Create a handle for `count` independent cavities (count > 1 is the batched
+ * Reynolds sweep: every cavity advances in the same calls).
+ *   p          host array[count] of parameters; read during the call only.
+ *   d_ws       caller-owned device buffer of ws_bytes bytes (>= the size from
+ *              cavity_workspace_bytes), 256-byte aligned, kept alive and
+ *              untouched by the caller until cavity_destroy.
+ *   hip_stream hipStream_t (NULL = null stream) all work is enqueued on.
+ *   out        receives the handle.
+ * The initial state is omega0 (or rest), psi solved from it with the compact
+ * equation (Sec. 3) and the wall vorticity set by Thom's formula (Sec. 3.1).
+ * Synchronises the stream.  Errors: EINVAL, ENOMEM, EHIP, ENOCONV, ENONFINITE.
+ */
+int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_bytes,
+                  void* hip_stream, cavity_t* out);
+
+/*
+ * Advance every cavity by nsteps SSPRK(5,4) steps (eqs. SSPRK54_1-5).  Each
+ * stage evaluates eq. (Lwn) with eq. (vel), combines interior nodes, solves
+ * the compact stream equation by four-colour SOR (eq. SequationFinal) to
+ * poisson_tol, and refreshes the wall vorticity by Thom's formula.
+ *   stats  nullable host array[count]; when given, the monitors of the last
+ *          step are computed and the call synchronises the stream.
+ * Returns ENOCONV if any solve hit its sweep limit (state still valid),
+ * ENONFINITE if a residual was not finite (handle poisoned), ESTATE on a
+ * poisoned handle.
+ */
+int cavity_step(cavity_t h, int32_t nsteps, cavity_stats* stats);
+
+/*
+ * Solve the compact stream equation for cavity idx.
+ *   d_omega  nullable device n*n vorticity (walls included, used as given);
+ *            NULL solves for the handle's current vorticity in place.
+ *   d_psi    nullable device n*n output for psi.
+ *   info     nullable host result; when given the call synchronises.
+ * With d_omega != NULL the handle's state is not modified.
+ */
+int cavity_poisson(cavity_t h, int32_t idx, const double* d_omega, double* d_psi,
+                   cavity_poisson_info* info);
+
+/*
+ * Copy out the fields of cavity idx as device n*n double arrays; each pointer
+ * is nullable.  u, v follow eq. (vel) inside and the wall values of Sec. 3.1
+ * (u = U on the lid row except its corners, 0 elsewhere; v = 0 on walls).
+ */
+int cavity_fields(cavity_t h, int32_t idx, double* d_psi, double* d_omega, double* d_u,
+                  double* d_v);
+
+/*
+ * Apply `sweeps` relaxation sweeps of eq. (SequationFinal) in four-colour
+ * order (rounded up to a whole number of kernel launches) to a scratch copy
+ * of cavity idx's psi, for the right-hand side of its current vorticity,
+ * with no convergence check and no host synchronisation.  The handle's state
+ * is not modified; the relaxed field can be read with cavity_fields only
+ * through `d_psi_out` here (nullable device n*n).  Writes the number of
+ * sweeps performed to *done (nullable).  Used to time the smoother alone.
+ */
+int cavity_relax(cavity_t h, int32_t idx, int32_t sweeps, double* d_psi_out, int64_t* done);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+int cavity_destroy(cavity_t h);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* cavity_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CAVITY_H */

@@ -1,0 +1,286 @@
+"""ctypes binding of ``libcavity.so`` (the C ABI in ``include/cavity.h``).
+
+Argument marshalling only: every step of the time stepper runs in the HIP
+library.  PyTorch supplies device memory (the workspace and field tensors)
+and the stream.  The functions carry the C names; :class:`Cavity` wraps them.
+
+There is no fallback: if the library is missing this module raises on import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcavity.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0809_3098_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ----------------------------------------------------------------- status
+CAVITY_OK = 0
+CAVITY_EINVAL = -1
+CAVITY_ENOMEM = -2
+CAVITY_EHIP = -3
+CAVITY_ENOCONV = -4
+CAVITY_ENONFINITE = -5
+CAVITY_ESTATE = -6
+CAVITY_FP64 = 0
+CAVITY_MIXED = 1
+
+_STATUS_NAMES = {0: "CAVITY_OK", -1: "CAVITY_EINVAL", -2: "CAVITY_ENOMEM", -3: "CAVITY_EHIP",
+                 -4: "CAVITY_ENOCONV", -5: "CAVITY_ENONFINITE", -6: "CAVITY_ESTATE"}
+
+
+class CavityError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+        self.message = message
+
+
+# ------------------------------------------------------------------ structs
+class cavity_params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("re", ctypes.c_double), ("u_lid", ctypes.c_double), ("nu", ctypes.c_double),
+        ("dt", ctypes.c_double), ("cfl", ctypes.c_double), ("poisson_tol", ctypes.c_double),
+        ("poisson_max_sweeps", ctypes.c_int32), ("resume", ctypes.c_int32),
+        ("sor_omega", ctypes.c_double),
+        ("omega0", ctypes.c_void_p), ("psi0", ctypes.c_void_p),
+    ]
+
+
+class cavity_stats(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("t", ctypes.c_double), ("dt", ctypes.c_double),
+        ("res_psi", ctypes.c_double), ("res_omega", ctypes.c_double),
+        ("domega_inf_over_dt", ctypes.c_double), ("ke", ctypes.c_double),
+        ("last_resid_inf", ctypes.c_double), ("sweeps_total", ctypes.c_int64),
+        ("sweeps_last_step", ctypes.c_int64), ("floor_limited", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class cavity_poisson_info(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("resid_inf", ctypes.c_double),
+                ("floor_limited", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.POINTER
+_lib.cavity_workspace_bytes.argtypes = [_P(cavity_params), ctypes.c_int32, _P(ctypes.c_size_t)]
+_lib.cavity_create.argtypes = [_P(cavity_params), ctypes.c_int32, ctypes.c_void_p,
+                               ctypes.c_size_t, ctypes.c_void_p, _P(ctypes.c_void_p)]
+_lib.cavity_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(cavity_stats)]
+_lib.cavity_poisson.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                ctypes.c_void_p, _P(cavity_poisson_info)]
+_lib.cavity_fields.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p]
+_lib.cavity_relax.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                              _P(ctypes.c_int64)]
+_lib.cavity_destroy.argtypes = [ctypes.c_void_p]
+_lib.cavity_last_error.restype = ctypes.c_char_p
+for _f in ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_poisson",
+           "cavity_fields", "cavity_relax", "cavity_destroy"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTED = ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_poisson",
+            "cavity_fields", "cavity_relax", "cavity_destroy", "cavity_last_error")
+
+
+def cavity_last_error() -> str:
+    return (_lib.cavity_last_error() or b"").decode()
+
+
+def _check(rc: int, allow=()):
+    if rc != CAVITY_OK and rc not in allow:
+        raise CavityError(rc, cavity_last_error())
+    return rc
+
+
+# ------------------------------------------------------------------ params
+@dataclass
+class Params:
+    """Python mirror of ``cavity_params`` (device pointers set by the caller)."""
+    n: int
+    re: float = 1000.0
+    u_lid: float = 1.0
+    nu: float = 0.0
+    dt: float = 0.0
+    cfl: float = 0.5
+    poisson_tol: float = 1e-10
+    poisson_max_sweeps: int = 0
+    precision: int = CAVITY_FP64
+    sor_omega: float = 0.0
+    resume: int = 0
+
+    def to_c(self, omega0_ptr: int = 0, psi0_ptr: int = 0) -> cavity_params:
+        return cavity_params(n=self.n, precision=self.precision, re=self.re, u_lid=self.u_lid,
+                             nu=self.nu, dt=self.dt, cfl=self.cfl, poisson_tol=self.poisson_tol,
+                             poisson_max_sweeps=self.poisson_max_sweeps, resume=self.resume,
+                             sor_omega=self.sor_omega, omega0=omega0_ptr or None,
+                             psi0=psi0_ptr or None)
+
+
+def _param_array(params: Sequence[cavity_params]):
+    arr = (cavity_params * len(params))()
+    for k, p in enumerate(params):
+        arr[k] = p
+    return arr
+
+
+# --------------------------------------------------------------- functions
+def cavity_workspace_bytes(params: Sequence[cavity_params]) -> int:
+    arr = _param_array(params)
+    out = ctypes.c_size_t(0)
+    _check(_lib.cavity_workspace_bytes(arr, len(params), ctypes.byref(out)))
+    return int(out.value)
+
+
+def cavity_create(params: Sequence[cavity_params], ws_ptr: int, ws_bytes: int,
+                  stream_ptr: int, allow_noconv: bool = False) -> int:
+    arr = _param_array(params)
+    h = ctypes.c_void_p(0)
+    rc = _lib.cavity_create(arr, len(params), ctypes.c_void_p(ws_ptr), ws_bytes,
+                            ctypes.c_void_p(stream_ptr), ctypes.byref(h))
+    _check(rc, allow=(CAVITY_ENOCONV,) if allow_noconv else ())
+    return int(h.value)
+
+
+def cavity_step(h: int, nsteps: int, count: int = 1, want_stats: bool = True,
+                allow_noconv: bool = False):
+    stats = (cavity_stats * count)() if want_stats else None
+    rc = _lib.cavity_step(ctypes.c_void_p(h), nsteps, stats)
+    _check(rc, allow=(CAVITY_ENOCONV,) if allow_noconv else ())
+    return [s.as_dict() for s in stats] if want_stats else None
+
+
+def cavity_poisson(h: int, idx: int, omega_ptr: int = 0, psi_ptr: int = 0,
+                   want_info: bool = True, allow_noconv: bool = False):
+    info = cavity_poisson_info() if want_info else None
+    rc = _lib.cavity_poisson(ctypes.c_void_p(h), idx, ctypes.c_void_p(omega_ptr or None),
+                             ctypes.c_void_p(psi_ptr or None),
+                             ctypes.byref(info) if want_info else None)
+    _check(rc, allow=(CAVITY_ENOCONV,) if allow_noconv else ())
+    return info.as_dict() if want_info else None
+
+
+def cavity_fields(h: int, idx: int, psi_ptr: int = 0, omega_ptr: int = 0, u_ptr: int = 0,
+                  v_ptr: int = 0) -> None:
+    _check(_lib.cavity_fields(ctypes.c_void_p(h), idx, ctypes.c_void_p(psi_ptr or None),
+                              ctypes.c_void_p(omega_ptr or None), ctypes.c_void_p(u_ptr or None),
+                              ctypes.c_void_p(v_ptr or None)))
+
+
+def cavity_relax(h: int, idx: int, sweeps: int, psi_out_ptr: int = 0) -> int:
+    done = ctypes.c_int64(0)
+    _check(_lib.cavity_relax(ctypes.c_void_p(h), idx, sweeps, ctypes.c_void_p(psi_out_ptr or None),
+                             ctypes.byref(done)))
+    return int(done.value)
+
+
+def cavity_destroy(h: int) -> None:
+    _check(_lib.cavity_destroy(ctypes.c_void_p(h)))
+
+
+# ------------------------------------------------------------ convenience
+class Cavity:
+    """One or more cavities on one GPU; torch supplies memory and the stream.
+
+    ``omega0`` / ``psi0`` are optional lists (per cavity) of n x n float64
+    numpy arrays or CUDA tensors.
+    """
+
+    def __init__(self, params: Sequence[Params] | Params, device: str = "cuda:0",
+                 omega0: Optional[Sequence] = None, psi0: Optional[Sequence] = None,
+                 stream=None, allow_noconv: bool = False):
+        import torch
+        self._torch = torch
+        if isinstance(params, Params):
+            params = [params]
+        self.params = list(params)
+        self.count = len(self.params)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        keep = []
+
+        def dev(a):
+            if a is None:
+                return 0
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+            t = t.to(device=self.device, dtype=torch.float64).contiguous()
+            keep.append(t)
+            return t.data_ptr()
+
+        cps = []
+        for k, p in enumerate(self.params):
+            w = dev(omega0[k]) if omega0 is not None else 0
+            s = dev(psi0[k]) if psi0 is not None else 0
+            cps.append(p.to_c(w, s))
+        nbytes = cavity_workspace_bytes(cps)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self.handle = cavity_create(cps, self.workspace.data_ptr(), nbytes,
+                                    self.stream.cuda_stream, allow_noconv=allow_noconv)
+        del keep
+
+    def step(self, nsteps: int = 1, want_stats: bool = True, allow_noconv: bool = False):
+        return cavity_step(self.handle, nsteps, self.count, want_stats, allow_noconv)
+
+    def poisson(self, idx: int = 0, omega=None, want_psi: bool = True, allow_noconv=False):
+        torch = self._torch
+        n = self.params[idx].n
+        w = None
+        if omega is not None:
+            w = omega if isinstance(omega, torch.Tensor) else torch.from_numpy(
+                np.ascontiguousarray(omega))
+            w = w.to(device=self.device, dtype=torch.float64).contiguous()
+        out = torch.empty((n, n), dtype=torch.float64, device=self.device) if want_psi else None
+        info = cavity_poisson(self.handle, idx, w.data_ptr() if w is not None else 0,
+                              out.data_ptr() if out is not None else 0, True, allow_noconv)
+        self.stream.synchronize()
+        return (out.cpu().numpy() if out is not None else None), info
+
+    def fields_tensors(self, idx: int = 0):
+        torch = self._torch
+        n = self.params[idx].n
+        t = [torch.empty((n, n), dtype=torch.float64, device=self.device) for _ in range(4)]
+        cavity_fields(self.handle, idx, *(x.data_ptr() for x in t))
+        self.stream.synchronize()
+        return t
+
+    def fields(self, idx: int = 0):
+        """psi, omega, u, v of cavity idx as numpy arrays [j, i]."""
+        return tuple(x.cpu().numpy() for x in self.fields_tensors(idx))
+
+    def relax(self, sweeps: int, idx: int = 0, want_psi: bool = False):
+        """Enqueue `sweeps` smoother sweeps on a scratch copy of psi (no sync)."""
+        out = None
+        if want_psi:
+            n = self.params[idx].n
+            out = self._torch.empty((n, n), dtype=self._torch.float64, device=self.device)
+        done = cavity_relax(self.handle, idx, sweeps, out.data_ptr() if out is not None else 0)
+        return done, out
+
+    def close(self):
+        if getattr(self, "handle", 0):
+            cavity_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

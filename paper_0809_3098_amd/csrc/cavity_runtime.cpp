@@ -1,0 +1,649 @@
+// Host runtime and C ABI of the driven-lid-cavity time stepper.
+//
+// Sequencing of a time step (N. Cardoso and P. Bicudo, arXiv:0809.3098,
+// Sec. 3): five SSPRK(5,4) stages (eqs. SSPRK54_1-5).  Each stage
+//   1. evaluates L(omega) of eq. (Lwn) with u, v of eq. (vel) and forms the
+//      stage's interior vorticity; the stage keeps the wall vorticity of the
+//      stage it was computed from;
+//   2. assembles the right-hand side of the compact stream equation and
+//      relaxes psi by four-colour SOR (eq. SequationFinal) until the residual
+//      max-norm is below the tolerance;
+//   3. refreshes the wall vorticity from psi by Thom's formula (Sec. 3.1).
+// The work is enqueued on one HIP stream.  A Poisson solve's stopping
+// decision lives in device memory, so sweeps are enqueued in chunks and the
+// host only reads the decision once per chunk.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cavity.h"
+#include "cavity_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+// SSPRK(5,4) Shu-Osher coefficients, Sec. 3 eqs. (SSPRK54_1)-(SSPRK54_5).
+// alpha_21 is printed as 0.555626506348765, which leaves the stage-2
+// coefficients summing to 0.999997; a Shu-Osher stage is a convex
+// combination, so alpha_21 = 1 - alpha_20 is used.  c_10 is printed to 11
+// digits; the 15-digit value satisfying the first-order condition with the
+// other coefficients is used.
+constexpr double kC10 = 0.391752226571890;
+constexpr double kA20 = 0.444370493651235, kA21 = 0.555629506348765, kB21 = 0.368410593050371;
+constexpr double kA30 = 0.620101851488403, kA32 = 0.379898148511597, kB32 = 0.251891774271694;
+constexpr double kA40 = 0.178079954393132, kA43 = 0.821920045606868, kB43 = 0.544974750228521;
+constexpr double kA52 = 0.517231671970585, kA53 = 0.096059710526147, kB53 = 0.063692468666290;
+constexpr double kA54 = 0.386708617503269, kB54 = 0.226007483236906;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Member {
+  cavity_params p{};
+  int n = 0, pitch = 0;
+  bool mixed = false;
+  double h = 0, nu = 0, dt = 0, u_lid = 0, tol = 0, relax = 0;
+  long long max_sweeps = 0, stall_window = 0;
+  // device fields (pitched)
+  double* w[4] = {nullptr, nullptr, nullptr, nullptr};  // w[0] = omega^n
+  double* psi = nullptr;       // current psi (solve result always lands here)
+  double* psi_b = nullptr;     // ping-pong partner
+  double* psi_prev = nullptr;  // psi^n for the monitors; scratch between steps
+  double* F = nullptr;
+  float* R32 = nullptr;
+  float* d32a = nullptr;
+  float* d32b = nullptr;
+  cav::PoissonCtl* ctl = nullptr;
+  double* diag_partial = nullptr;
+  double* diag_out = nullptr;
+  int diag_np = 0;
+  cav::SorConfig cfg64{64, 64, 2, 0};
+  cav::SorConfig cfg32{64, 64, 2, 0};
+  int inner_sweeps = 0;  // mixed: FP32 sweeps per refinement round
+  // host-side state
+  long long step = 0;
+  double t = 0;
+  long long sweeps_total = 0, sweeps_step = 0;
+  double est_sweeps = 0;  // running estimate of sweeps per solve
+  int floor_step = 0;
+  int status_step = CAVITY_OK;
+  double last_resid = 0;
+};
+
+}  // namespace
+
+struct cavity_s {
+  int count = 0;
+  int device = 0;
+  hipStream_t st = nullptr;
+  bool poisoned = false;
+  std::vector<Member> m;
+  cav::PoissonCtl* host_ctl = nullptr;  // pinned readback of every member's ctl
+  double* host_diag = nullptr;          // pinned readback, 4 per member
+};
+
+namespace {
+
+#define HIP_TRY(h, expr)                                                         \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      if (h) (h)->poisoned = true;                                               \
+      return fail(CAVITY_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+    }                                                                            \
+  } while (0)
+
+int pitch_of(int n) { return (n + 31) / 32 * 32; }
+
+// Validation and derived quantities (Sec. 3.2: Re = |U| L / nu, L = 1).
+int derive(const cavity_params& p, Member& m) {
+  if (p.n < 5 || p.n > 16385) return fail(CAVITY_EINVAL, "n = %d outside [5, 16385]", p.n);
+  if (p.resume != 0 && p.resume != 1) return fail(CAVITY_EINVAL, "resume must be 0 or 1");
+  if (p.resume && (!p.omega0 || !p.psi0))
+    return fail(CAVITY_EINVAL, "resume = 1 needs both omega0 and psi0");
+  if (p.precision != CAVITY_FP64 && p.precision != CAVITY_MIXED)
+    return fail(CAVITY_EINVAL, "precision = %d is not CAVITY_FP64 or CAVITY_MIXED", p.precision);
+  const double vals[] = {p.re, p.u_lid, p.nu, p.dt, p.cfl, p.poisson_tol, p.sor_omega};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(CAVITY_EINVAL, "non-finite parameter");
+  m.p = p;
+  m.n = p.n;
+  m.pitch = pitch_of(p.n);
+  m.mixed = p.precision == CAVITY_MIXED;
+  m.h = 1.0 / (p.n - 1);
+  m.u_lid = p.u_lid;
+  if (p.nu > 0) {
+    m.nu = p.nu;
+  } else {
+    if (!(p.re > 0)) return fail(CAVITY_EINVAL, "re must be > 0 (got %g)", p.re);
+    m.nu = std::fabs(p.u_lid) / p.re;
+  }
+  if (p.dt > 0) {
+    m.dt = p.dt;
+  } else {
+    if (p.u_lid == 0) return fail(CAVITY_EINVAL, "dt must be > 0 when u_lid == 0");
+    const double cfl = p.cfl > 0 ? p.cfl : 0.5;
+    m.dt = cfl * m.h / std::fabs(p.u_lid);
+  }
+  m.tol = p.poisson_tol > 0 ? p.poisson_tol : 1e-10;
+  m.max_sweeps = p.poisson_max_sweeps > 0 ? p.poisson_max_sweeps : 200LL * p.n;
+  if (p.sor_omega > 0) {
+    if (!(p.sor_omega < 2.0)) return fail(CAVITY_EINVAL, "sor_omega must lie in (0, 2)");
+    m.relax = p.sor_omega;
+  } else {
+    m.relax = 2.0 / (1.0 + std::sin(M_PI * m.h));
+  }
+  // A stalled over-relaxation sits at its rounding floor; allow several
+  // residual halvings' worth of sweeps (about 0.11 (n-1) each) before polishing.
+  m.stall_window = std::max<long long>(64, 2LL * p.n);
+  // tiles: small grids favour more, smaller blocks
+  if (p.n <= 320) {
+    m.cfg64 = {32, 32, 1, 0};
+    m.cfg32 = {32, 32, 1, 0};
+  } else {
+    m.cfg64 = {64, 64, 2, 0};
+    m.cfg32 = {64, 64, 2, 0};
+  }
+  // Mixed precision: FP32 sweeps per refinement round, enough for about
+  // three decades of residual reduction of the correction.
+  {
+    const int unit = 2 * m.cfg32.s;
+    const int want = (int)std::ceil(1.5 * (p.n - 1));
+    m.inner_sweeps = std::max(unit, (want + unit - 1) / unit * unit);
+  }
+  return CAVITY_OK;
+}
+
+size_t member_bytes(const Member& m) {
+  const size_t f64 = align_up((size_t)m.n * m.pitch * sizeof(double));
+  const size_t f32 = align_up((size_t)m.n * m.pitch * sizeof(float));
+  size_t b = 8 * f64;  // w[4], psi, psi_b, psi_prev, F
+  if (m.mixed) b += 3 * f32;
+  b += align_up(sizeof(cav::PoissonCtl));
+  b += align_up((size_t)cav::diag_partials(m.n) * 4 * sizeof(double));
+  b += align_up(4 * sizeof(double));
+  return b;
+}
+
+void carve(Member& m, char*& cur) {
+  const size_t f64 = align_up((size_t)m.n * m.pitch * sizeof(double));
+  const size_t f32 = align_up((size_t)m.n * m.pitch * sizeof(float));
+  auto take = [&](size_t bytes) {
+    char* r = cur;
+    cur += bytes;
+    return r;
+  };
+  for (int k = 0; k < 4; ++k) m.w[k] = reinterpret_cast<double*>(take(f64));
+  m.psi = reinterpret_cast<double*>(take(f64));
+  m.psi_b = reinterpret_cast<double*>(take(f64));
+  m.psi_prev = reinterpret_cast<double*>(take(f64));
+  m.F = reinterpret_cast<double*>(take(f64));
+  if (m.mixed) {
+    m.R32 = reinterpret_cast<float*>(take(f32));
+    m.d32a = reinterpret_cast<float*>(take(f32));
+    m.d32b = reinterpret_cast<float*>(take(f32));
+  }
+  m.ctl = reinterpret_cast<cav::PoissonCtl*>(take(align_up(sizeof(cav::PoissonCtl))));
+  m.diag_np = cav::diag_partials(m.n);
+  m.diag_partial = reinterpret_cast<double*>(take(align_up((size_t)m.diag_np * 4 * 8)));
+  m.diag_out = reinterpret_cast<double*>(take(align_up(4 * sizeof(double))));
+}
+
+// ---------------------------------------------------------------------------
+// Poisson solves.  All members listed in `idx` are solved together: their
+// sweeps are interleaved chunk by chunk and one readback serves them all.
+// Each solve starts from the psi in Member::psi and leaves its result there;
+// F must already hold the right-hand side.
+// ---------------------------------------------------------------------------
+int reset_ctl(cavity_s* h, Member& m) {
+  const double tol_hat = m.tol * 0.3 * m.h * m.h;  // (g - psi) = (3 h^2 / 10) r
+  const long long spc = m.mixed ? m.inner_sweeps : 2LL * m.cfg64.s;
+  HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, m.stall_window, spc,
+                                   h->st));
+  return CAVITY_OK;
+}
+
+// One chunk of work for member m: `units` sweep pairs (FP64) or refinement
+// rounds (mixed).  Every launch returns at once once the solve has stopped.
+int enqueue_chunk(cavity_s* h, Member& m, int units) {
+  for (int u = 0; u < units; ++u) {
+    if (!m.mixed) {
+      HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi, m.psi_b, m.F, m.n, m.pitch, m.ctl, 0, h->st));
+      HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi_b, m.psi, m.F, m.n, m.pitch, m.ctl, 1, h->st));
+    } else {
+      HIP_TRY(h, cav::launch_resid64(m.psi, m.F, m.R32, m.d32a, m.n, m.pitch, m.ctl, h->st));
+      const int pairs = m.inner_sweeps / (2 * m.cfg32.s);
+      for (int q = 0; q < pairs; ++q) {
+        // the last pair relaxes with 1 (Gauss-Seidel) to damp the FP32
+        // over-relaxation noise before the correction is applied
+        const double rl = (q == pairs - 1) ? 1.0 : m.relax;
+        HIP_TRY(h, cav::launch_sor32(m.cfg32, m.d32a, m.d32b, m.R32, m.n, m.pitch, m.ctl, rl,
+                                     h->st));
+        HIP_TRY(h, cav::launch_sor32(m.cfg32, m.d32b, m.d32a, m.R32, m.n, m.pitch, m.ctl, rl,
+                                     h->st));
+      }
+      HIP_TRY(h, cav::launch_refine(m.psi, m.d32a, m.n, m.pitch, m.ctl, m.inner_sweeps, h->st));
+    }
+  }
+  return CAVITY_OK;
+}
+
+// Enqueue a residual check without sweeping (FP64): a converged warm start
+// then needs no sweep at all.
+int enqueue_initial_check(cavity_s* h, Member& m) {
+  if (m.mixed) return CAVITY_OK;  // the first refinement round starts with a check
+  HIP_TRY(h, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, h->st));
+  return CAVITY_OK;
+}
+
+int read_ctls(cavity_s* h, const std::vector<int>& idx) {
+  for (int k : idx)
+    HIP_TRY(h, hipMemcpyAsync(&h->host_ctl[k], h->m[k].ctl, sizeof(cav::PoissonCtl),
+                              hipMemcpyDeviceToHost, h->st));
+  HIP_TRY(h, hipStreamSynchronize(h->st));
+  return CAVITY_OK;
+}
+
+int solve_members(cavity_s* h, const std::vector<int>& idx) {
+  int rc;
+  for (int k : idx) {
+    Member& m = h->m[k];
+    if ((rc = reset_ctl(h, m)) != CAVITY_OK) return rc;
+    if ((rc = enqueue_initial_check(h, m)) != CAVITY_OK) return rc;
+  }
+  std::vector<int> active = idx;
+  std::vector<long long> enqueued(h->count, 0);
+  bool first = true;
+  while (!active.empty()) {
+    for (int k : active) {
+      Member& m = h->m[k];
+      const long long per_unit = m.mixed ? m.inner_sweeps : 2LL * m.cfg64.s;
+      long long units;
+      if (first && m.est_sweeps > 0)
+        units = (long long)std::ceil(1.05 * m.est_sweeps / per_unit);
+      else if (first)
+        units = std::max<long long>(4, (long long)(0.5 * (m.n - 1) / per_unit));
+      else
+        units = std::max<long long>(2, enqueued[k] / 4);
+      units = std::max<long long>(1, std::min<long long>(units, m.max_sweeps / per_unit + 1));
+      if ((rc = enqueue_chunk(h, m, (int)units)) != CAVITY_OK) return rc;
+      enqueued[k] += units;
+    }
+    first = false;
+    if ((rc = read_ctls(h, active)) != CAVITY_OK) return rc;
+    std::vector<int> still;
+    for (int k : active) {
+      const cav::PoissonCtl& c = h->host_ctl[k];
+      if (c.state != cav::SOLVE_RUN) continue;
+      Member& m = h->m[k];
+      const long long per_unit = m.mixed ? m.inner_sweeps : 2LL * m.cfg64.s;
+      if (enqueued[k] * per_unit > 2 * m.max_sweeps + 64 * per_unit) {
+        // the device never stopped the solve: a defect, not a slow solve
+        h->poisoned = true;
+        return fail(CAVITY_EHIP, "Poisson solve of cavity %d made no decision after %lld sweeps",
+                    k, enqueued[k] * per_unit);
+      }
+      still.push_back(k);
+    }
+    active.swap(still);
+  }
+  int worst = CAVITY_OK;
+  for (int k : idx) {
+    Member& m = h->m[k];
+    const cav::PoissonCtl& c = h->host_ctl[k];
+    m.sweeps_step += c.sweeps;
+    m.sweeps_total += c.sweeps;
+    m.last_resid = c.last * (10.0 / 3.0) / (m.h * m.h);
+    if (c.sweeps > 0)
+      m.est_sweeps = m.est_sweeps > 0 ? 0.5 * (m.est_sweeps + c.sweeps) : (double)c.sweeps;
+    if (c.state == cav::SOLVE_FLOOR) m.floor_step = 1;
+    if (c.state == cav::SOLVE_NONFINITE) {
+      h->poisoned = true;
+      return fail(CAVITY_ENONFINITE, "non-finite Poisson residual in cavity %d", k);
+    }
+    if (c.state == cav::SOLVE_NOCONV) {
+      m.status_step = CAVITY_ENOCONV;
+      worst = fail(CAVITY_ENOCONV, "Poisson solve of cavity %d hit %lld sweeps (residual %g)", k,
+                   (long long)c.sweeps, m.last_resid);
+    }
+  }
+  return worst;
+}
+
+int enqueue_rhs_and_walls_prep(cavity_s* h, Member& m, const double* omega) {
+  HIP_TRY(h, cav::launch_poisson_rhs(omega, m.F, m.n, m.pitch, m.h, h->st));
+  return CAVITY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One SSPRK(5,4) step of every member, stage by stage.
+// Buffers: w[0] = omega^n, w[1] = omega^(1), omega^(3), omega^(n+1);
+// w[2] = omega^(2), then the stage-5 partial sum P; w[3] = omega^(4).
+// ---------------------------------------------------------------------------
+int step_all(cavity_s* h, bool want_diag) {
+  int rc, worst = CAVITY_OK;
+  std::vector<int> all(h->count);
+  for (int k = 0; k < h->count; ++k) all[k] = k;
+  for (Member& m : h->m) {
+    m.sweeps_step = 0;
+    m.floor_step = 0;
+    m.status_step = CAVITY_OK;
+    if (want_diag) HIP_TRY(h, cav::launch_copy(m.psi, m.psi_prev, m.n, m.pitch, h->st));
+  }
+  for (int stage = 1; stage <= 5; ++stage) {
+    for (Member& m : h->m) {
+      cav::StageArgs a{};
+      a.nu = m.nu;
+      a.h = m.h;
+      const double dt = m.dt;
+      const double* w0 = nullptr;
+      const double* win = nullptr;
+      const double* wx = nullptr;
+      double* out = nullptr;
+      const double* wp = nullptr;
+      double* pout = nullptr;
+      switch (stage) {
+        case 1:
+          win = m.w[0]; out = m.w[1]; a.a1 = 1.0; a.b = kC10 * dt;
+          break;
+        case 2:
+          w0 = m.w[0]; win = m.w[1]; out = m.w[2]; a.a0 = kA20; a.a1 = kA21; a.b = kB21 * dt;
+          break;
+        case 3:
+          w0 = m.w[0]; win = m.w[2]; out = m.w[1]; a.a0 = kA30; a.a1 = kA32; a.b = kB32 * dt;
+          break;
+        case 4:
+          w0 = m.w[0]; win = m.w[1]; out = m.w[3]; a.a0 = kA40; a.a1 = kA43; a.b = kB43 * dt;
+          wp = m.w[2]; pout = m.w[2]; a.pa = kA52; a.pb = kA53; a.pl = kB53 * dt;
+          break;
+        default:
+          win = m.w[3]; wx = m.w[2]; out = m.w[1]; a.a1 = kA54; a.ax = 1.0; a.b = kB54 * dt;
+          break;
+      }
+      HIP_TRY(h, cav::launch_stage(m.psi, w0, win, wx, out, wp, pout, m.n, m.pitch, a, h->st));
+      if ((rc = enqueue_rhs_and_walls_prep(h, m, out)) != CAVITY_OK) return rc;
+    }
+    rc = solve_members(h, all);
+    if (rc == CAVITY_ENONFINITE || rc == CAVITY_EHIP) return rc;
+    if (rc != CAVITY_OK) worst = rc;
+    for (Member& m : h->m) {
+      double* out = (stage == 2) ? m.w[2] : (stage == 4) ? m.w[3] : m.w[1];
+      HIP_TRY(h, cav::launch_thom(m.psi, out, m.n, m.pitch, m.h, m.u_lid, h->st));
+    }
+  }
+  for (Member& m : h->m) {
+    std::swap(m.w[0], m.w[1]);  // omega^(n+1) becomes the state; omega^n kept in w[1]
+    m.step += 1;
+    m.t += m.dt;
+    if (want_diag)
+      HIP_TRY(h, cav::launch_diag(m.psi_prev, m.psi, m.w[1], m.w[0], m.n, m.pitch, m.h,
+                                  m.diag_partial, m.diag_np, m.diag_out, h->st));
+  }
+  return worst;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* cavity_last_error(void) { return g_err.c_str(); }
+
+int cavity_workspace_bytes(const cavity_params* p, int32_t count, size_t* bytes) {
+  if (!p || !bytes) return fail(CAVITY_EINVAL, "null argument");
+  if (count < 1) return fail(CAVITY_EINVAL, "count must be >= 1");
+  size_t total = 0;
+  for (int k = 0; k < count; ++k) {
+    Member m;
+    const int rc = derive(p[k], m);
+    if (rc != CAVITY_OK) return rc;
+    total += member_bytes(m);
+  }
+  *bytes = total;
+  return CAVITY_OK;
+}
+
+int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_bytes,
+                  void* hip_stream, cavity_t* out) {
+  if (!p || !out) return fail(CAVITY_EINVAL, "null argument");
+  *out = nullptr;
+  if (count < 1) return fail(CAVITY_EINVAL, "count must be >= 1");
+  if (!d_ws) return fail(CAVITY_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign != 0)
+    return fail(CAVITY_EINVAL, "workspace must be 256-byte aligned");
+  cavity_s* h = new (std::nothrow) cavity_s();
+  if (!h) return fail(CAVITY_ENOMEM, "host allocation failed");
+  h->count = count;
+  h->st = static_cast<hipStream_t>(hip_stream);
+  h->m.resize(count);
+  size_t need = 0;
+  for (int k = 0; k < count; ++k) {
+    const int rc = derive(p[k], h->m[k]);
+    if (rc != CAVITY_OK) {
+      delete h;
+      return rc;
+    }
+    need += member_bytes(h->m[k]);
+  }
+  if (ws_bytes < need) {
+    delete h;
+    return fail(CAVITY_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  }
+  if (hipGetDevice(&h->device) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&h->host_ctl), count * sizeof(cav::PoissonCtl)) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&h->host_diag), count * 4 * sizeof(double)) !=
+          hipSuccess) {
+    cavity_destroy(h);
+    return fail(CAVITY_EHIP, "pinned host allocation failed");
+  }
+  char* cur = static_cast<char*>(d_ws);
+  for (Member& m : h->m) carve(m, cur);
+
+  auto bail = [&](int rc) {
+    cavity_destroy(h);
+    return rc;
+  };
+  for (Member& m : h->m) {
+    for (int k = 0; k < 4; ++k)
+      if (cav::launch_fill(m.w[k], m.n, m.pitch, 0.0, h->st) != hipSuccess)
+        return bail(fail(CAVITY_EHIP, "fill failed"));
+    double* f64[] = {m.psi, m.psi_b, m.psi_prev, m.F};
+    for (double* f : f64)
+      if (cav::launch_fill(f, m.n, m.pitch, 0.0, h->st) != hipSuccess)
+        return bail(fail(CAVITY_EHIP, "fill failed"));
+    if (m.mixed) {
+      float* f32[] = {m.R32, m.d32a, m.d32b};
+      for (float* f : f32)
+        if (cav::launch_fill32(f, m.n, m.pitch, 0.0f, h->st) != hipSuccess)
+          return bail(fail(CAVITY_EHIP, "fill failed"));
+    }
+    if (m.p.omega0 && cav::launch_copy_in(m.p.omega0, m.w[0], m.n, m.pitch, h->st) != hipSuccess)
+      return bail(fail(CAVITY_EHIP, "omega0 copy failed"));
+    if (m.p.psi0) {
+      if (cav::launch_copy_in(m.p.psi0, m.psi_b, m.n, m.pitch, h->st) != hipSuccess ||
+          cav::launch_copy_interior(m.psi_b, m.psi, m.n, m.pitch, h->st) != hipSuccess)
+        return bail(fail(CAVITY_EHIP, "psi0 copy failed"));
+    }
+    m.p.omega0 = nullptr;
+    m.p.psi0 = nullptr;
+    int rc = enqueue_rhs_and_walls_prep(h, m, m.w[0]);
+    if (rc != CAVITY_OK) return bail(rc);
+  }
+  // The initial state: psi solved for omega0, then Thom's wall vorticity.
+  // A resumed member already holds such a pair and is taken as it is.
+  std::vector<int> fresh;
+  for (int k = 0; k < count; ++k)
+    if (!h->m[k].p.resume) fresh.push_back(k);
+  int rc = fresh.empty() ? CAVITY_OK : solve_members(h, fresh);
+  if (rc == CAVITY_ENONFINITE || rc == CAVITY_EHIP) return bail(rc);
+  for (int k : fresh) {
+    Member& m = h->m[k];
+    if (cav::launch_thom(m.psi, m.w[0], m.n, m.pitch, m.h, m.u_lid, h->st) != hipSuccess)
+      return bail(fail(CAVITY_EHIP, "thom failed"));
+  }
+  if (hipStreamSynchronize(h->st) != hipSuccess) return bail(fail(CAVITY_EHIP, "sync failed"));
+  for (Member& m : h->m) {
+    m.sweeps_total = 0;
+    m.sweeps_step = 0;
+  }
+  *out = h;
+  return rc;
+}
+
+int cavity_step(cavity_t h, int32_t nsteps, cavity_stats* stats) {
+  if (!h) return fail(CAVITY_EINVAL, "null handle");
+  if (h->poisoned) return fail(CAVITY_ESTATE, "handle poisoned by an earlier failure");
+  if (nsteps < 0) return fail(CAVITY_EINVAL, "nsteps must be >= 0");
+  HIP_TRY(h, hipSetDevice(h->device));
+  int worst = CAVITY_OK;
+  for (int s = 0; s < nsteps; ++s) {
+    const bool diag = stats && s == nsteps - 1;
+    const int rc = step_all(h, diag);
+    if (rc == CAVITY_ENONFINITE || rc == CAVITY_EHIP) return rc;
+    if (rc != CAVITY_OK) worst = rc;
+  }
+  if (stats) {
+    for (int k = 0; k < h->count; ++k) {
+      Member& m = h->m[k];
+      if (nsteps > 0)
+        HIP_TRY(h, hipMemcpyAsync(&h->host_diag[4 * k], m.diag_out, 4 * sizeof(double),
+                                  hipMemcpyDeviceToHost, h->st));
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->st));
+    for (int k = 0; k < h->count; ++k) {
+      Member& m = h->m[k];
+      cavity_stats& o = stats[k];
+      std::memset(&o, 0, sizeof o);
+      o.step = m.step;
+      o.t = m.t;
+      o.dt = m.dt;
+      if (nsteps > 0) {
+        const double* d = &h->host_diag[4 * k];
+        o.res_psi = d[0] / m.n;
+        o.res_omega = d[1] / m.n;
+        o.domega_inf_over_dt = d[2] / m.dt;
+        o.ke = 0.5 * m.h * m.h * d[3];
+      }
+      o.last_resid_inf = m.last_resid;
+      o.sweeps_total = m.sweeps_total;
+      o.sweeps_last_step = m.sweeps_step;
+      o.floor_limited = m.floor_step;
+      o.status = m.status_step;
+    }
+  }
+  return worst;
+}
+
+int cavity_poisson(cavity_t h, int32_t idx, const double* d_omega, double* d_psi,
+                   cavity_poisson_info* info) {
+  if (!h) return fail(CAVITY_EINVAL, "null handle");
+  if (h->poisoned) return fail(CAVITY_ESTATE, "handle poisoned by an earlier failure");
+  if (idx < 0 || idx >= h->count) return fail(CAVITY_EINVAL, "idx %d out of range", idx);
+  HIP_TRY(h, hipSetDevice(h->device));
+  Member& m = h->m[idx];
+  int rc;
+  double* saved_psi = m.psi;
+  double* saved_b = m.psi_b;
+  if (d_omega) {
+    // Solve for a caller-given vorticity from a zero start without touching
+    // the state: w[3] holds the input, psi_prev / psi_b the iterate.
+    HIP_TRY(h, cav::launch_copy_in(d_omega, m.w[3], m.n, m.pitch, h->st));
+    HIP_TRY(h, cav::launch_fill(m.psi_prev, m.n, m.pitch, 0.0, h->st));
+    m.psi = m.psi_prev;
+    m.psi_b = saved_b;
+    if ((rc = enqueue_rhs_and_walls_prep(h, m, m.w[3])) != CAVITY_OK) return rc;
+  } else {
+    if ((rc = enqueue_rhs_and_walls_prep(h, m, m.w[0])) != CAVITY_OK) return rc;
+  }
+  const long long before = m.sweeps_total;
+  rc = solve_members(h, std::vector<int>{idx});
+  double* result = m.psi;
+  m.psi = saved_psi;
+  m.psi_b = saved_b;
+  if (rc == CAVITY_ENONFINITE || rc == CAVITY_EHIP) return rc;
+  if (!d_omega)
+    HIP_TRY(h, cav::launch_thom(m.psi, m.w[0], m.n, m.pitch, m.h, m.u_lid, h->st));
+  if (d_psi) HIP_TRY(h, cav::launch_copy_out(result, d_psi, m.n, m.pitch, h->st));
+  if (info) {
+    HIP_TRY(h, hipStreamSynchronize(h->st));
+    const cav::PoissonCtl& c = h->host_ctl[idx];
+    info->sweeps = m.sweeps_total - before;
+    info->resid_inf = c.last * (10.0 / 3.0) / (m.h * m.h);
+    info->floor_limited = c.state == cav::SOLVE_FLOOR ? 1 : 0;
+    info->status = c.state == cav::SOLVE_NOCONV ? CAVITY_ENOCONV : CAVITY_OK;
+  }
+  return rc;
+}
+
+int cavity_fields(cavity_t h, int32_t idx, double* d_psi, double* d_omega, double* d_u,
+                  double* d_v) {
+  if (!h) return fail(CAVITY_EINVAL, "null handle");
+  if (h->poisoned) return fail(CAVITY_ESTATE, "handle poisoned by an earlier failure");
+  if (idx < 0 || idx >= h->count) return fail(CAVITY_EINVAL, "idx %d out of range", idx);
+  if ((d_u == nullptr) != (d_v == nullptr))
+    return fail(CAVITY_EINVAL, "u and v must be requested together");
+  HIP_TRY(h, hipSetDevice(h->device));
+  Member& m = h->m[idx];
+  if (d_psi) HIP_TRY(h, cav::launch_copy_out(m.psi, d_psi, m.n, m.pitch, h->st));
+  if (d_omega) HIP_TRY(h, cav::launch_copy_out(m.w[0], d_omega, m.n, m.pitch, h->st));
+  if (d_u) HIP_TRY(h, cav::launch_velocity(m.psi, m.n, m.pitch, m.h, m.u_lid, d_u, d_v, h->st));
+  return CAVITY_OK;
+}
+
+int cavity_relax(cavity_t h, int32_t idx, int32_t sweeps, double* d_psi_out, int64_t* done) {
+  if (!h) return fail(CAVITY_EINVAL, "null handle");
+  if (h->poisoned) return fail(CAVITY_ESTATE, "handle poisoned by an earlier failure");
+  if (idx < 0 || idx >= h->count) return fail(CAVITY_EINVAL, "idx %d out of range", idx);
+  if (sweeps < 0) return fail(CAVITY_EINVAL, "sweeps must be >= 0");
+  HIP_TRY(h, hipSetDevice(h->device));
+  Member& m = h->m[idx];
+  // Scratch: psi_prev / psi_b hold the iterate, F the right-hand side.  The
+  // control block is reset with an unreachable tolerance so that no launch
+  // returns early.
+  HIP_TRY(h, cav::launch_copy(m.psi, m.psi_prev, m.n, m.pitch, h->st));
+  HIP_TRY(h, cav::launch_poisson_rhs(m.w[0], m.F, m.n, m.pitch, m.h, h->st));
+  HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, -1.0, 1LL << 62, 1LL << 62, 0, h->st));
+  const int per = m.cfg64.s;
+  const int launches = (sweeps + 2 * per - 1) / (2 * per) * 2;
+  for (int k = 0; k < launches; k += 2) {
+    HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi_prev, m.psi_b, m.F, m.n, m.pitch, m.ctl, 0,
+                                 h->st));
+    HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi_b, m.psi_prev, m.F, m.n, m.pitch, m.ctl, 0,
+                                 h->st));
+  }
+  if (d_psi_out) HIP_TRY(h, cav::launch_copy_out(m.psi_prev, d_psi_out, m.n, m.pitch, h->st));
+  if (done) *done = (int64_t)launches * per;
+  return CAVITY_OK;
+}
+
+int cavity_destroy(cavity_t h) {
+  if (!h) return CAVITY_OK;
+  if (h->host_ctl) (void)hipHostFree(h->host_ctl);
+  if (h->host_diag) (void)hipHostFree(h->host_diag);
+  delete h;
+  return CAVITY_OK;
+}
+
+}  // extern "C"

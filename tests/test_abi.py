@@ -1,0 +1,96 @@
+"""The C-ABI library builds, loads and exports every symbol of include/cavity.h.
+
+Runs without a GPU: only host-side entry points that touch no device are
+called (workspace sizing and argument validation).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cavity.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cavity_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def binding():
+    lib = os.path.join(ROOT, "paper_0809_3098_amd", "libcavity.so")
+    if not os.path.exists(lib):
+        from paper_0809_3098_amd.build import build
+        build()
+    import paper_0809_3098_amd.cavity as b
+    return b
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for f in ("cavity_create", "cavity_step", "cavity_poisson", "cavity_fields",
+              "cavity_destroy", "cavity_last_error", "cavity_workspace_bytes"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(binding):
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert set(binding.EXPORTED) <= set(_declared_functions())
+
+
+def test_struct_layout_matches_header(binding):
+    # offsets of the C structs as laid out by a C compiler for this header
+    assert ctypes.sizeof(binding.cavity_params) == 88
+    assert binding.cavity_params.omega0.offset == 72
+    assert ctypes.sizeof(binding.cavity_stats) == 88
+    assert ctypes.sizeof(binding.cavity_poisson_info) == 24
+
+
+def test_workspace_bytes_scales_with_grid(binding):
+    P = binding.Params
+    small = binding.cavity_workspace_bytes([P(n=64).to_c()])
+    big = binding.cavity_workspace_bytes([P(n=1024).to_c()])
+    assert big > 200 * small / 2
+    # eight FP64 fields of 1024 x 1024 at least
+    assert big >= 8 * 1024 * 1024 * 8
+    mixed = binding.cavity_workspace_bytes([P(n=1024, precision=binding.CAVITY_MIXED).to_c()])
+    assert mixed >= big + 3 * 1024 * 1024 * 4
+    two = binding.cavity_workspace_bytes([P(n=64).to_c(), P(n=1024).to_c()])
+    assert two == small + big
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n=4), "n ="),
+    (dict(n=64, re=0.0), "re must"),
+    (dict(n=64, re=float("nan")), "non-finite"),
+    (dict(n=64, u_lid=0.0), "dt must"),
+    (dict(n=64, sor_omega=2.0), "sor_omega"),
+    (dict(n=64, precision=7), "precision"),
+    (dict(n=64, resume=1), "resume"),
+])
+def test_invalid_parameters_are_rejected(binding, kw, msg):
+    with pytest.raises(binding.CavityError) as e:
+        binding.cavity_workspace_bytes([binding.Params(**kw).to_c()])
+    assert e.value.code == binding.CAVITY_EINVAL
+    assert msg in e.value.message
+
+
+def test_create_rejects_before_touching_a_device(binding):
+    P = binding.Params
+    with pytest.raises(binding.CavityError) as e:
+        binding.cavity_create([P(n=3).to_c()], 256, 1 << 20, 0)
+    assert e.value.code == binding.CAVITY_EINVAL
+    with pytest.raises(binding.CavityError) as e:
+        binding.cavity_create([P(n=64).to_c()], 256 + 8, 1 << 30, 0)
+    assert "aligned" in e.value.message
+    with pytest.raises(binding.CavityError) as e:
+        binding.cavity_create([P(n=64).to_c()], 256, 16, 0)
+    assert e.value.code == binding.CAVITY_ENOMEM
+    with pytest.raises(binding.CavityError) as e:
+        binding.cavity_step(0, 1)
+    assert e.value.code == binding.CAVITY_EINVAL
