@@ -107,7 +107,8 @@ def main():
     ev1.record(stream)
     ev1.synchronize()
     relax_ms = ev0.elapsed_time(ev1)
-    sweeps_per_launch = 2 if n > 320 else 1
+    tun = cav.tuning(0)
+    sweeps_per_launch = tun["sweeps_per_launch"]
     launches = done // sweeps_per_launch
     per_launch_s = relax_ms / 1e3 / launches
     cells = (n - 2) ** 2
@@ -116,8 +117,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": _traffic(args.workload),
-                "kernel": f"k_sor<double,64,64,{sweeps_per_launch}>" if n > 320 else
-                          "k_sor<double,32,32,1>",
+                "kernel": (f"k_sor<double,{tun['tile_x']},{tun['tile_y']},"
+                           f"{sweeps_per_launch},{tun['threads']}>"),
                 "alg_bytes_per_launch": alg_bytes,
                 "avg_launch_us": round(per_launch_s * 1e6, 3)}
     cav.close()

@@ -171,14 +171,46 @@ int cavity_fields(cavity_t h, int32_t idx, double* d_psi, double* d_omega, doubl
 
 /*
  * Apply `sweeps` relaxation sweeps of eq. (SequationFinal) in four-colour
- * order (rounded up to a whole number of kernel launches) to a scratch copy
- * of cavity idx's psi, for the right-hand side of its current vorticity,
- * with no convergence check and no host synchronisation.  The handle's state
- * is not modified; the relaxed field can be read with cavity_fields only
- * through `d_psi_out` here (nullable device n*n).  Writes the number of
- * sweeps performed to *done (nullable).  Used to time the smoother alone.
+ * order (rounded up to a whole number of kernel launches) with no convergence
+ * check and no host synchronisation; the handle's state is not modified.
+ *   arith 0: FP64 sweeps on a scratch copy of cavity idx's psi for the
+ *            right-hand side of its current vorticity; the result is copied to
+ *            d_psi_out (nullable device n*n).
+ *   arith 1: FP32 sweeps of the correction equation for the FP64 residual of
+ *            the current psi (cavity idx must be CAVITY_MIXED); d_psi_out must
+ *            be NULL.
+ * Writes the number of sweeps performed to *done (nullable).  Used to time
+ * the smoothers alone and to apply a fixed number of sweeps.
  */
-int cavity_relax(cavity_t h, int32_t idx, int32_t sweeps, double* d_psi_out, int64_t* done);
+int cavity_relax(cavity_t h, int32_t idx, int32_t sweeps, int32_t arith, double* d_psi_out,
+                 int64_t* done);
+
+/*
+ * Launch configuration of a cavity's Poisson smoother.  The sweep kernel loads
+ * a tile_x x tile_y tile of psi and of the right-hand side plus a halo into
+ * LDS and runs sweeps_per_launch four-colour sweeps there; only compiled
+ * combinations are accepted (EINVAL otherwise).  Results do not depend on the
+ * tile shape or thread count; sweeps_per_launch, check_every and sor_omega
+ * change the sweep schedule and so the last bits of the converged result.
+ */
+typedef struct cavity_tuning {
+  int32_t tile_x, tile_y;        /* FP64 sweep kernel tile (nodes)                 */
+  int32_t sweeps_per_launch;     /* sweeps per FP64 launch                          */
+  int32_t threads;               /* threads per block of the FP64 kernel            */
+  int32_t tile_x32, tile_y32;    /* FP32 correction sweeps (CAVITY_MIXED)          */
+  int32_t sweeps_per_launch32;
+  int32_t threads32;
+  int32_t check_every;           /* FP64: sweeps between residual checks (rounded
+                                    up to whole launch pairs)                     */
+  int32_t inner_sweeps;          /* mixed: FP32 sweeps per refinement round        */
+  int32_t xcd_bands;             /* 1: each XCD relaxes a contiguous band of tiles */
+  int32_t reserved;
+  double sor_omega;              /* relaxation parameter in (0, 2)                 */
+} cavity_tuning;
+
+/* Read / replace the launch configuration of cavity idx (host only). */
+int cavity_get_tuning(cavity_t h, int32_t idx, cavity_tuning* t);
+int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t);
 
 /* Release the handle (host memory only; the workspace stays the caller's). */
 int cavity_destroy(cavity_t h);

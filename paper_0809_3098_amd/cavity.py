@@ -79,6 +79,21 @@ class cavity_poisson_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class cavity_tuning(ctypes.Structure):
+    _fields_ = [
+        ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+        ("sweeps_per_launch", ctypes.c_int32), ("threads", ctypes.c_int32),
+        ("tile_x32", ctypes.c_int32), ("tile_y32", ctypes.c_int32),
+        ("sweeps_per_launch32", ctypes.c_int32), ("threads32", ctypes.c_int32),
+        ("check_every", ctypes.c_int32), ("inner_sweeps", ctypes.c_int32),
+        ("xcd_bands", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("sor_omega", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 _P = ctypes.POINTER
 _lib.cavity_workspace_bytes.argtypes = [_P(cavity_params), ctypes.c_int32, _P(ctypes.c_size_t)]
 _lib.cavity_create.argtypes = [_P(cavity_params), ctypes.c_int32, ctypes.c_void_p,
@@ -88,16 +103,20 @@ _lib.cavity_poisson.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p
                                 ctypes.c_void_p, _P(cavity_poisson_info)]
 _lib.cavity_fields.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p]
-_lib.cavity_relax.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
-                              _P(ctypes.c_int64)]
+_lib.cavity_relax.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.c_void_p, _P(ctypes.c_int64)]
+_lib.cavity_get_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(cavity_tuning)]
+_lib.cavity_set_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(cavity_tuning)]
 _lib.cavity_destroy.argtypes = [ctypes.c_void_p]
 _lib.cavity_last_error.restype = ctypes.c_char_p
 for _f in ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_poisson",
-           "cavity_fields", "cavity_relax", "cavity_destroy"):
+           "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
+           "cavity_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_poisson",
-            "cavity_fields", "cavity_relax", "cavity_destroy", "cavity_last_error")
+            "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
+            "cavity_destroy", "cavity_last_error")
 
 
 def cavity_last_error() -> str:
@@ -184,11 +203,28 @@ def cavity_fields(h: int, idx: int, psi_ptr: int = 0, omega_ptr: int = 0, u_ptr:
                               ctypes.c_void_p(v_ptr or None)))
 
 
-def cavity_relax(h: int, idx: int, sweeps: int, psi_out_ptr: int = 0) -> int:
+def cavity_relax(h: int, idx: int, sweeps: int, arith: int = 0, psi_out_ptr: int = 0) -> int:
     done = ctypes.c_int64(0)
-    _check(_lib.cavity_relax(ctypes.c_void_p(h), idx, sweeps, ctypes.c_void_p(psi_out_ptr or None),
-                             ctypes.byref(done)))
+    _check(_lib.cavity_relax(ctypes.c_void_p(h), idx, sweeps, arith,
+                             ctypes.c_void_p(psi_out_ptr or None), ctypes.byref(done)))
     return int(done.value)
+
+
+def cavity_get_tuning(h: int, idx: int) -> dict:
+    t = cavity_tuning()
+    _check(_lib.cavity_get_tuning(ctypes.c_void_p(h), idx, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def cavity_set_tuning(h: int, idx: int, **kw) -> dict:
+    t = cavity_tuning()
+    _check(_lib.cavity_get_tuning(ctypes.c_void_p(h), idx, ctypes.byref(t)))
+    for k, v in kw.items():
+        if k not in t.as_dict():
+            raise KeyError(k)
+        setattr(t, k, v)
+    _check(_lib.cavity_set_tuning(ctypes.c_void_p(h), idx, ctypes.byref(t)))
+    return cavity_get_tuning(h, idx)
 
 
 def cavity_destroy(h: int) -> None:
@@ -265,14 +301,21 @@ class Cavity:
         """psi, omega, u, v of cavity idx as numpy arrays [j, i]."""
         return tuple(x.cpu().numpy() for x in self.fields_tensors(idx))
 
-    def relax(self, sweeps: int, idx: int = 0, want_psi: bool = False):
-        """Enqueue `sweeps` smoother sweeps on a scratch copy of psi (no sync)."""
+    def relax(self, sweeps: int, idx: int = 0, want_psi: bool = False, arith: int = 0):
+        """Enqueue `sweeps` smoother sweeps on scratch buffers (no sync)."""
         out = None
         if want_psi:
             n = self.params[idx].n
             out = self._torch.empty((n, n), dtype=self._torch.float64, device=self.device)
-        done = cavity_relax(self.handle, idx, sweeps, out.data_ptr() if out is not None else 0)
+        done = cavity_relax(self.handle, idx, sweeps, arith,
+                            out.data_ptr() if out is not None else 0)
         return done, out
+
+    def tuning(self, idx: int = 0) -> dict:
+        return cavity_get_tuning(self.handle, idx)
+
+    def set_tuning(self, idx: int = 0, **kw) -> dict:
+        return cavity_set_tuning(self.handle, idx, **kw)
 
     def close(self):
         if getattr(self, "handle", 0):

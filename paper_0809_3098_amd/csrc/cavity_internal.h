@@ -40,14 +40,53 @@ struct alignas(128) PoissonCtl {
   long long sweeps_per_check; // sweeps between two checks
   int floor_limited;
   int pad0;
+  // Totals over every solve since the handle was created (never reset by a
+  // solve), read by the host once per call.
+  long long total_sweeps;
+  int total_floor;            // solves that stopped at the rounding floor
+  int total_noconv;           // solves that hit the sweep limit
+  int total_nonfinite;        // solves that met NaN / Inf
+  int total_solves;
+};
+
+// One cavity of a persistent batched solve (device-resident descriptor).
+struct BatchMember {
+  double* psi;
+  double* psi_b;
+  const double* F;
+  PoissonCtl* ctl;
+  double* part;        // two doubles per tile
+  float* R32;
+  float* d32a;
+  float* d32b;
+  int n, pitch;
+  int tiles_x, tiles;  // tiles of this cavity in the batch's tile shape
+  int tile0;           // first tile of this cavity in the batch tile list
+  int pad;
+};
+
+// Grid barrier and error flag of the persistent kernels.
+struct alignas(128) BatchCtl {
+  unsigned int bar_count;
+  unsigned int bar_gen;
+  int error;           // 1: a barrier wait timed out (blocks not co-resident)
+  int pad;
 };
 
 // Tile configuration of the temporally blocked four-colour sweep.
 struct SorConfig {
   int tx, ty;      // output tile (nodes)
   int s;           // sweeps per launch
+  int nt;          // threads per block
   int xcd_bands;   // 1: remap blocks so each XCD owns a band of tile rows
 };
+
+// Whether (tx, ty, s, nt) is one of the compiled sweep kernels.
+bool sor_config_supported(const SorConfig& c, bool fp32);
+// Upper bound on the blocks of any sweep launch (smallest tile) and of the
+// residual kernel: sizes the partial-maximum array.
+int sor_max_blocks(int n);
+int resid_blocks();
 
 // ---- launches (all enqueue on `st`, return hipError_t) --------------------
 
@@ -68,9 +107,10 @@ struct StageArgs {
   double pa, pb, pl;          // p_out coefficients (pl includes dt)
   double nu, h;
 };
-hipError_t launch_stage(const double* psi, const double* w0, const double* win,
-                        const double* wx, double* out, const double* wp, double* p_out,
-                        int n, int pitch, const StageArgs& a, hipStream_t st);
+// psi32 != nullptr: L is evaluated in FP32 from that shadow of psi (mixed).
+hipError_t launch_stage(const double* psi, const float* psi32, const double* w0,
+                        const double* win, const double* wx, double* out, const double* wp,
+                        double* p_out, int n, int pitch, const StageArgs& a, hipStream_t st);
 
 // Reset a solve's control block (a kernel, so it can live in a graph).
 hipError_t launch_ctl_reset(PoissonCtl* ctl, double relax, double tol_hat,
@@ -79,16 +119,35 @@ hipError_t launch_ctl_reset(PoissonCtl* ctl, double relax, double tol_hat,
 
 // One launch of `cfg.s` four-colour sweeps, psi_in -> psi_out (ping-pong).
 // check != 0: also the residual of the result and the solve decision.
+// `part` holds two doubles per block for the check's partial maxima.
 hipError_t launch_sor64(const SorConfig& cfg, const double* psi_in, double* psi_out,
-                        const double* F, int n, int pitch, PoissonCtl* ctl, int check,
-                        hipStream_t st);
+                        const double* F, int n, int pitch, PoissonCtl* ctl, double* part,
+                        int check, hipStream_t st);
 hipError_t launch_sor32(const SorConfig& cfg, const float* d_in, float* d_out, const float* R,
                         int n, int pitch, PoissonCtl* ctl, double relax, hipStream_t st);
+
+// Persistent batched solves: every member's Poisson solve runs in one launch;
+// blocks sweep the batch's tile list round by round with grid barriers in
+// between and decide each member's stop in device memory.  The grid must be
+// co-resident (see batch_grid); barrier waits are bounded by spin_ticks of the
+// 100 MHz wall clock and set BatchCtl::error when exceeded.
+// FP64: pairs_per_check launch-pairs of cfg.s sweeps between checks.
+hipError_t launch_batch64(const SorConfig& cfg, const BatchMember* mem, int count,
+                          int total_tiles, int pairs_per_check, BatchCtl* bc, int grid,
+                          long long spin_ticks, hipStream_t st);
+// Mixed: rounds of FP64 residual, inner_pairs FP32 launch-pairs (the last
+// pair Gauss-Seidel) and FP64 refinement.
+hipError_t launch_batch_mixed(const SorConfig& cfg32, const BatchMember* mem, int count,
+                              int total_tiles, int inner_pairs, BatchCtl* bc, int grid,
+                              long long spin_ticks, hipStream_t st);
+// Largest co-resident grid for the batched kernel of this configuration.
+int batch_grid(const SorConfig& cfg, bool mixed, int device);
+bool batch_config_supported(const SorConfig& cfg, bool mixed);
 
 // Mixed precision: FP64 residual r = g(psi) - psi into R32 (as float), zero
 // d32, reduce max |r| and take the solve decision.
 hipError_t launch_resid64(const double* psi, const double* F, float* R32, float* d32, int n,
-                          int pitch, PoissonCtl* ctl, hipStream_t st);
+                          int pitch, PoissonCtl* ctl, double* part, hipStream_t st);
 // psi64 += d32 on interior nodes and count the inner sweeps (skipped once
 // the solve has stopped).
 hipError_t launch_refine(double* psi, const float* d32, int n, int pitch, PoissonCtl* ctl,
@@ -109,6 +168,8 @@ hipError_t launch_velocity(const double* psi, int n, int pitch, double h, double
 // Pitched <-> dense copies and fills.
 hipError_t launch_fill(double* a, int n, int pitch, double value, hipStream_t st);
 hipError_t launch_fill32(float* a, int n, int pitch, float value, hipStream_t st);
+// b = (float)a over the whole pitched array.
+hipError_t launch_shadow(const double* a, float* b, int n, int pitch, hipStream_t st);
 hipError_t launch_copy_in(const double* dense, double* pitched, int n, int pitch,
                           hipStream_t st);
 hipError_t launch_copy_out(const double* pitched, double* dense, int n, int pitch,

@@ -10,6 +10,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "cavity_internal.h"
 
 namespace cav {
@@ -20,7 +22,7 @@ constexpr int kBlock = 256;
 constexpr int kPolishChecks = 2;   // checks of Gauss-Seidel polish before giving up
 
 // ---------------------------------------------------------------------------
-// Block reductions (wavefront shuffles, then LDS across the four waves).
+// Block reductions (wavefront shuffles, then LDS across the waves).
 // ---------------------------------------------------------------------------
 __device__ inline double wave_max(double v) {
 #pragma unroll
@@ -28,15 +30,10 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // Max over the block of two non-negative values; result valid in thread 0.
+template <int NT>
 __device__ inline void block_max2(double& a, double& b) {
-  __shared__ double red[2][kBlock / 64];
+  __shared__ double red[2][NT / 64];
   a = wave_max(a);
   b = wave_max(b);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -46,7 +43,7 @@ __device__ inline void block_max2(double& a, double& b) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < kBlock / 64; ++w) {
+    for (int w = 1; w < NT / 64; ++w) {
       a = fmax(a, red[0][w]);
       b = fmax(b, red[1][w]);
     }
@@ -63,6 +60,7 @@ __device__ inline double mag(double r) {
 // r is max |g - psi| in the units of the relaxation formula.
 __device__ void decide(PoissonCtl* c, double r, double pm, long long sweeps_done) {
   c->sweeps += sweeps_done;
+  c->total_sweeps += sweeps_done;
   c->last = r;
   c->psimax = pm;
   int st = SOLVE_RUN;
@@ -91,25 +89,75 @@ __device__ void decide(PoissonCtl* c, double r, double pm, long long sweeps_done
     }
     if (st == SOLVE_RUN && c->sweeps >= c->max_sweeps) st = SOLVE_NOCONV;
   }
+  if (st != SOLVE_RUN) {
+    c->total_solves += 1;
+    if (st == SOLVE_FLOOR) c->total_floor += 1;
+    if (st == SOLVE_NOCONV) c->total_noconv += 1;
+    if (st == SOLVE_NONFINITE) c->total_nonfinite += 1;
+  }
   c->state = st;
 }
 
-// Thread 0 of every block of a checking launch: publish the block maxima;
-// the last block to arrive reduces them and decides.
-__device__ void finish_check(PoissonCtl* ctl, double rmax, double pmax, long long sweeps_done) {
-  atomicMax(&ctl->rbits, (unsigned long long)__double_as_longlong(rmax));
-  atomicMax(&ctl->pbits, (unsigned long long)__double_as_longlong(pmax));
-  __threadfence();
-  const unsigned int nblocks = gridDim.x * gridDim.y;
-  const unsigned int t = atomicAdd(&ctl->ticket, 1u);
-  if (t == nblocks - 1) {
+// As check_and_decide, for maxima already reduced over the block (valid in
+// thread 0).
+template <int NT>
+__device__ void check_and_decide_reduced(PoissonCtl* ctl, double* part, double rmax, double pmax,
+                                         long long sweeps_done) {
+  __shared__ int s_last;
+  const unsigned int nb = gridDim.x * gridDim.y;
+  const unsigned int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0) {
+    part[2 * bid] = rmax;
+    part[2 * bid + 1] = pmax;
     __threadfence();
-    const double r = __longlong_as_double((long long)atomicAdd(&ctl->rbits, 0ull));
-    const double pm = __longlong_as_double((long long)atomicAdd(&ctl->pbits, 0ull));
-    ctl->rbits = 0ull;
-    ctl->pbits = 0ull;
+    const unsigned int t = atomicAdd(&ctl->ticket, 1u);
+    s_last = (t == nb - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double r = 0.0, p = 0.0;
+  for (unsigned int k = threadIdx.x; k < nb; k += NT) {
+    r = fmax(r, part[2 * k]);
+    p = fmax(p, part[2 * k + 1]);
+  }
+  block_max2<NT>(r, p);
+  if (threadIdx.x == 0) {
     ctl->ticket = 0u;
-    decide(ctl, r, pm, sweeps_done);
+    decide(ctl, r, p, sweeps_done < 0 ? ctl->sweeps_per_check : sweeps_done);
+  }
+}
+
+// Called by every thread of every block of a checking launch with its local
+// maxima.  Each block stores its maxima in `part` and takes one ticket; the
+// block holding the last ticket reduces all partial maxima and decides.  One
+// same-address atomic per block keeps the cost flat in the block count.
+template <int NT>
+__device__ void check_and_decide(PoissonCtl* ctl, double* part, double rmax, double pmax,
+                                 long long sweeps_done) {
+  __shared__ int s_last;
+  block_max2<NT>(rmax, pmax);
+  const unsigned int nb = gridDim.x * gridDim.y;
+  const unsigned int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0) {
+    part[2 * bid] = rmax;
+    part[2 * bid + 1] = pmax;
+    __threadfence();
+    const unsigned int t = atomicAdd(&ctl->ticket, 1u);
+    s_last = (t == nb - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double r = 0.0, p = 0.0;
+  for (unsigned int k = threadIdx.x; k < nb; k += NT) {
+    r = fmax(r, part[2 * k]);
+    p = fmax(p, part[2 * k + 1]);
+  }
+  block_max2<NT>(r, p);
+  if (threadIdx.x == 0) {
+    ctl->ticket = 0u;
+    decide(ctl, r, p, sweeps_done < 0 ? ctl->sweeps_per_check : sweeps_done);
   }
 }
 
@@ -151,40 +199,64 @@ __device__ inline T fma_t(T a, T b, T c) { return fma(a, b, c); }
 template <>
 __device__ inline float fma_t<float>(float a, float b, float c) { return fmaf(a, b, c); }
 
-template <typename T, int TX, int TY, int S, bool CHECK>
-__global__ __launch_bounds__(kBlock) void k_sor(const T* __restrict__ pin, T* __restrict__ pout,
-                                                const T* __restrict__ F, int n, int pitch,
-                                                PoissonCtl* __restrict__ ctl, int tiles_x,
-                                                int xcd_bands, double relax_arg) {
-  using G = SorGeom<T, TX, TY, S>;
-  __shared__ T sp[4 * G::PLANE];
-  __shared__ T sf[4 * G::PLANE];
-  if (ctl->state != SOLVE_RUN) return;
-  const T w = (T)(relax_arg > 0.0 ? relax_arg : ctl->relax);
+template <typename T> struct Pair;
+template <> struct Pair<double> { using type = double2; };
+template <> struct Pair<float> { using type = float2; };
 
-  const int nb = gridDim.x;
-  int tile = blockIdx.x;
-  if (xcd_bands && (nb & 7) == 0) tile = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+// One tile of S sweeps, shared by the per-launch kernel and the persistent
+// batched kernel.  sp / sf are the block's LDS planes.  With CHECK the
+// block-wide maxima of |g - psi| and |psi| over the tile are returned in
+// thread 0's rmax / pmax.
+template <typename T, int TX, int TY, int S, int NT, bool CHECK>
+__device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restrict__ pout,
+                                         const T* __restrict__ F, int n, int pitch, int tile,
+                                         int tiles_x, T w, T* sp, T* sf, double& rmax_out,
+                                         double& pmax_out) {
+  using G = SorGeom<T, TX, TY, S>;
+  using T2 = typename Pair<T>::type;
   const int tyi = tile / tiles_x;
   const int txi = tile - tyi * tiles_x;
   const int x0 = txi * TX - G::H;  // region origin, even
   const int y0 = tyi * TY - G::H;
   const int tid = threadIdx.x;
 
-  // Region load: rows of RX nodes, coalesced along x.
-  for (int idx = tid; idx < G::RX * G::RY; idx += kBlock) {
-    const int ly = idx / G::RX;
-    const int lx = idx - ly * G::RX;
-    const int gx = x0 + lx, gy = y0 + ly;
-    T v = T(0), f = T(0);
-    if ((unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n) {
-      const size_t g = (size_t)gy * pitch + gx;
-      v = pin[g];
-      f = F[g];
+  // Region load in pairs of nodes (x even, x odd), coalesced along x.  All
+  // global loads of a thread are issued before its LDS stores.
+  constexpr int RXP = G::RX / 2;
+  constexpr int NPAIR = RXP * G::RY;
+  constexpr int NL = (NPAIR + NT - 1) / NT;
+  T2 lv[NL], lf[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int idx = tid + k * NT;
+    lv[k].x = lv[k].y = T(0);
+    lf[k].x = lf[k].y = T(0);
+    if (idx < NPAIR) {
+      const int ly = idx / RXP;
+      const int gx = x0 + 2 * (idx - ly * RXP), gy = y0 + ly;
+      if ((unsigned)gy < (unsigned)n && gx >= 0) {
+        const size_t g = (size_t)gy * pitch + gx;
+        if (gx + 1 < n) {
+          lv[k] = *reinterpret_cast<const T2*>(pin + g);
+          lf[k] = *reinterpret_cast<const T2*>(F + g);
+        } else if (gx < n) {
+          lv[k].x = pin[g];
+          lf[k].x = F[g];
+        }
+      }
     }
-    const int o = (((ly & 1) << 1) | (lx & 1)) * G::PLANE + (ly >> 1) * G::RXH + (lx >> 1);
-    sp[o] = v;
-    sf[o] = f;
+  }
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int idx = tid + k * NT;
+    if (idx < NPAIR) {
+      const int ly = idx / RXP;
+      const int o = ((ly & 1) << 1) * G::PLANE + (ly >> 1) * G::RXH + (idx - ly * RXP);
+      sp[o] = lv[k].x;
+      sp[o + G::PLANE] = lv[k].y;
+      sf[o] = lf[k].x;
+      sf[o + G::PLANE] = lf[k].y;
+    }
   }
   __syncthreads();
 
@@ -206,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_sor(const T* __restrict__ pin, T* __
     const T* ns = sp + ((1 - cy) * 2 + cx) * G::PLANE;
     const T* dg = sp + ((1 - cy) * 2 + (1 - cx)) * G::PLANE;
     const T* ff = sf + (cy * 2 + cx) * G::PLANE;
-    for (int bb = b0 + wave; bb <= b1; bb += kBlock / 64) {
+    for (int bb = b0 + wave; bb <= b1; bb += NT / 64) {
       for (int aa = a0 + lane; aa <= a1; aa += 64) {
         const int o = bb * G::RXH + aa;
         const int oE = o + cx;                 // E at oE, W at oE - 1
@@ -224,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_sor(const T* __restrict__ pin, T* __
 
   // Write the tile; with CHECK also its residual max |g - psi| and max |psi|.
   double rmax = 0.0, pmax = 0.0;
-  for (int idx = tid; idx < TX * TY; idx += kBlock) {
+  for (int idx = tid; idx < TX * TY; idx += NT) {
     const int ty = idx / TX;
     const int lx = G::H + (idx - ty * TX);
     const int ly = G::H + ty;
@@ -246,9 +318,227 @@ __global__ __launch_bounds__(kBlock) void k_sor(const T* __restrict__ pin, T* __
       pmax = fmax(pmax, mag((double)p));
     }
   }
-  if (CHECK) {
-    block_max2(rmax, pmax);
-    if (tid == 0) finish_check(ctl, rmax, pmax, 2ll * S);
+  if (CHECK) block_max2<NT>(rmax, pmax);
+  rmax_out = rmax;
+  pmax_out = pmax;
+}
+
+template <typename T, int TX, int TY, int S, int NT, bool CHECK>
+__global__ __launch_bounds__(NT) void k_sor(const T* __restrict__ pin, T* __restrict__ pout,
+                                            const T* __restrict__ F, int n, int pitch,
+                                            PoissonCtl* __restrict__ ctl, double* __restrict__ part,
+                                            int tiles_x, int xcd_bands, double relax_arg) {
+  using G = SorGeom<T, TX, TY, S>;
+  __shared__ T sp[4 * G::PLANE];
+  __shared__ T sf[4 * G::PLANE];
+  if (ctl->state != SOLVE_RUN) return;
+  const T w = (T)(relax_arg > 0.0 ? relax_arg : ctl->relax);
+  const int nb = gridDim.x;
+  int tile = blockIdx.x;
+  if (xcd_bands && (nb & 7) == 0) tile = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  double rmax = 0.0, pmax = 0.0;
+  sor_tile<T, TX, TY, S, NT, CHECK>(pin, pout, F, n, pitch, tile, tiles_x, w, sp, sf, rmax, pmax);
+  if (CHECK) check_and_decide_reduced<NT>(ctl, part, rmax, pmax, -1);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched Poisson solves (several cavities of uneven size, one
+// launch).  The tile list concatenates every member's tiles; block b sweeps
+// tiles b, b + G, ... of each round.  A round is one launch-equivalent of the
+// per-launch path (S sweeps, psi_in -> psi_out), so results are bitwise those
+// of the per-launch path with the same tile shape and check spacing.
+// ---------------------------------------------------------------------------
+__device__ inline int load_state(const PoissonCtl* c) {
+  return __hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sense-reversing grid barrier.  Returns false (and sets bc->error) if a wait
+// exceeds spin_ticks of the wall clock, so a grid that is not co-resident
+// ends with an error instead of hanging.
+__device__ bool grid_sync(BatchCtl* bc, unsigned int nb, long long spin_ticks) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __threadfence();
+    const unsigned int g = __hip_atomic_load(&bc->bar_gen, __ATOMIC_ACQUIRE,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned int a = __hip_atomic_fetch_add(&bc->bar_count, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+    if (a == nb - 1) {
+      __hip_atomic_store(&bc->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bc->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const long long t0 = wall_clock64();
+      while (__hip_atomic_load(&bc->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(2);
+        if (__hip_atomic_load(&bc->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            wall_clock64() - t0 > spin_ticks) {
+          __hip_atomic_store(&bc->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    __threadfence();
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+__device__ inline int member_of(const BatchMember* mem, int count, int t) {
+  int k = 0;
+  while (k + 1 < count && t >= mem[k + 1].tile0) ++k;
+  return k;
+}
+
+// Any member still solving?  Read by thread 0, broadcast through LDS.
+__device__ bool any_running(const BatchMember* mem, int count) {
+  __shared__ int s_any;
+  if (threadIdx.x == 0) {
+    int any = 0;
+    for (int k = 0; k < count; ++k) any |= (load_state(mem[k].ctl) == SOLVE_RUN);
+    s_any = any;
+  }
+  __syncthreads();
+  const int r = s_any;
+  __syncthreads();
+  return r != 0;
+}
+
+// Block k reduces member k's partial maxima and takes its decision.
+template <int NT>
+__device__ void batch_decide(const BatchMember* mem, int count, long long sweeps_done) {
+  if ((int)blockIdx.x >= count) return;
+  const BatchMember& m = mem[blockIdx.x];
+  if (load_state(m.ctl) != SOLVE_RUN) return;
+  double r = 0.0, p = 0.0;
+  for (int q = threadIdx.x; q < m.tiles; q += NT) {
+    r = fmax(r, m.part[2 * q]);
+    p = fmax(p, m.part[2 * q + 1]);
+  }
+  block_max2<NT>(r, p);
+  if (threadIdx.x == 0)
+    decide(m.ctl, r, p, sweeps_done < 0 ? m.ctl->sweeps_per_check : sweeps_done);
+}
+
+template <int TX, int TY, int S, int NT>
+__global__ __launch_bounds__(NT) void k_batch64(const BatchMember* __restrict__ mem, int count,
+                                                int total_tiles, int pairs_per_check,
+                                                BatchCtl* __restrict__ bc, long long spin_ticks) {
+  using G = SorGeom<double, TX, TY, S>;
+  __shared__ double sp[4 * G::PLANE];
+  __shared__ double sf[4 * G::PLANE];
+  const unsigned int nb = gridDim.x;
+  while (any_running(mem, count)) {
+    for (int r = 0; r < 2 * pairs_per_check; ++r) {
+      const bool fwd = (r & 1) == 0;
+      const bool check = (r == 2 * pairs_per_check - 1);
+      for (int t = blockIdx.x; t < total_tiles; t += nb) {
+        const BatchMember& m = mem[member_of(mem, count, t)];
+        if (load_state(m.ctl) != SOLVE_RUN) continue;
+        const int lt = t - m.tile0;
+        const double w = m.ctl->relax;
+        const double* pin = fwd ? m.psi : m.psi_b;
+        double* pout = fwd ? m.psi_b : m.psi;
+        double rmax = 0.0, pmax = 0.0;
+        if (check) {
+          sor_tile<double, TX, TY, S, NT, true>(pin, pout, m.F, m.n, m.pitch, lt, m.tiles_x, w,
+                                                sp, sf, rmax, pmax);
+          if (threadIdx.x == 0) {
+            m.part[2 * lt] = rmax;
+            m.part[2 * lt + 1] = pmax;
+          }
+        } else {
+          sor_tile<double, TX, TY, S, NT, false>(pin, pout, m.F, m.n, m.pitch, lt, m.tiles_x, w,
+                                                 sp, sf, rmax, pmax);
+        }
+        __syncthreads();
+      }
+      if (!grid_sync(bc, nb, spin_ticks)) return;
+    }
+    batch_decide<NT>(mem, count, -1);
+    if (!grid_sync(bc, nb, spin_ticks)) return;
+  }
+}
+
+template <int TX, int TY, int S, int NT>
+__global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restrict__ mem,
+                                                    int count, int total_tiles, int inner_pairs,
+                                                    BatchCtl* __restrict__ bc,
+                                                    long long spin_ticks) {
+  using G = SorGeom<float, TX, TY, S>;
+  __shared__ float sp[4 * G::PLANE];
+  __shared__ float sf[4 * G::PLANE];
+  const unsigned int nb = gridDim.x;
+  for (;;) {
+    // FP64 residual of psi on every tile; the correction starts from zero.
+    for (int t = blockIdx.x; t < total_tiles; t += nb) {
+      const BatchMember& m = mem[member_of(mem, count, t)];
+      if (load_state(m.ctl) != SOLVE_RUN) continue;
+      const int lt = t - m.tile0;
+      const int tyi = lt / m.tiles_x, txi = lt - tyi * m.tiles_x;
+      double rmax = 0.0, pmax = 0.0;
+      for (int q = threadIdx.x; q < TX * TY; q += NT) {
+        const int i = txi * TX + q % TX, j = tyi * TY + q / TX;
+        if (i < 1 || i > m.n - 2 || j < 1 || j > m.n - 2) continue;
+        const size_t p = (size_t)j * m.pitch + i;
+        const double* psi = m.psi;
+        const int pt = m.pitch;
+        const double s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pt] + psi[p - pt]);
+        const double sd = (psi[p + pt + 1] + psi[p + pt - 1]) + (psi[p - pt + 1] + psi[p - pt - 1]);
+        const double r = fma(0.2, s4, fma(0.05, sd, m.F[p])) - psi[p];
+        m.R32[p] = (float)r;
+        m.d32a[p] = 0.0f;
+        rmax = fmax(rmax, mag(r));
+        pmax = fmax(pmax, mag(psi[p]));
+      }
+      block_max2<NT>(rmax, pmax);
+      if (threadIdx.x == 0) {
+        m.part[2 * lt] = rmax;
+        m.part[2 * lt + 1] = pmax;
+      }
+      __syncthreads();
+    }
+    if (!grid_sync(bc, nb, spin_ticks)) return;
+    batch_decide<NT>(mem, count, 0);
+    if (!grid_sync(bc, nb, spin_ticks)) return;
+    if (!any_running(mem, count)) return;
+    // FP32 correction sweeps; the last pair relaxes with 1.
+    for (int r = 0; r < 2 * inner_pairs; ++r) {
+      const bool fwd = (r & 1) == 0;
+      for (int t = blockIdx.x; t < total_tiles; t += nb) {
+        const BatchMember& m = mem[member_of(mem, count, t)];
+        if (load_state(m.ctl) != SOLVE_RUN) continue;
+        const float w = (r >= 2 * (inner_pairs - 1)) ? 1.0f : (float)m.ctl->relax;
+        double rm = 0.0, pm = 0.0;
+        sor_tile<float, TX, TY, S, NT, false>(fwd ? m.d32a : m.d32b, fwd ? m.d32b : m.d32a,
+                                              m.R32, m.n, m.pitch, t - m.tile0, m.tiles_x, w,
+                                              sp, sf, rm, pm);
+        __syncthreads();
+      }
+      if (!grid_sync(bc, nb, spin_ticks)) return;
+    }
+    // FP64 refinement psi += d, and the sweep count.
+    for (int t = blockIdx.x; t < total_tiles; t += nb) {
+      const BatchMember& m = mem[member_of(mem, count, t)];
+      if (load_state(m.ctl) != SOLVE_RUN) continue;
+      const int lt = t - m.tile0;
+      const int tyi = lt / m.tiles_x, txi = lt - tyi * m.tiles_x;
+      for (int q = threadIdx.x; q < TX * TY; q += NT) {
+        const int i = txi * TX + q % TX, j = tyi * TY + q / TX;
+        if (i < 1 || i > m.n - 2 || j < 1 || j > m.n - 2) continue;
+        const size_t p = (size_t)j * m.pitch + i;
+        m.psi[p] += (double)m.d32a[p];
+      }
+      if (lt == 0 && threadIdx.x == 0) {
+        const long long done = 2LL * S * inner_pairs;
+        m.ctl->sweeps += done;
+        m.ctl->total_sweeps += done;
+      }
+    }
+    if (!grid_sync(bc, nb, spin_ticks)) return;
   }
 }
 
@@ -265,7 +555,23 @@ __device__ inline double transport(const double* __restrict__ psi, const double*
   return adv + dif;
 }
 
+// The same operator in FP32 arithmetic, from an FP32 shadow of psi and the
+// FP64 vorticity rounded to FP32 (mixed precision).
+__device__ inline float transport32(const float* __restrict__ psi, const double* __restrict__ w,
+                                    size_t p, int pitch, float inv2h, float invh2, float nu) {
+  const float u = (psi[p + pitch] - psi[p - pitch]) * inv2h;
+  const float v = -(psi[p + 1] - psi[p - 1]) * inv2h;
+  const float wP = (float)w[p], wE = (float)w[p + 1], wW = (float)w[p - 1];
+  const float wN = (float)w[p + pitch], wS = (float)w[p - pitch];
+  const float adv = -u * ((wE - wW) * inv2h) - v * ((wN - wS) * inv2h);
+  const float dif = nu * (((wE - 2.0f * wP + wW) + (wN - 2.0f * wP + wS)) * invh2);
+  return adv + dif;
+}
+
+// psi32 == nullptr: L in FP64 from psi; otherwise L in FP32 from psi32.
+// The stage combination is FP64 either way.
 __global__ __launch_bounds__(kBlock) void k_stage(const double* __restrict__ psi,
+                                                  const float* __restrict__ psi32,
                                                   const double* __restrict__ w0,
                                                   const double* __restrict__ win,
                                                   const double* __restrict__ wx, double* out,
@@ -281,7 +587,9 @@ __global__ __launch_bounds__(kBlock) void k_stage(const double* __restrict__ psi
   }
   const double inv2h = 0.5 / a.h;
   const double invh2 = 1.0 / (a.h * a.h);
-  const double L = transport(psi, win, p, pitch, inv2h, invh2, a.nu);
+  const double L = psi32 ? (double)transport32(psi32, win, p, pitch, (float)inv2h, (float)invh2,
+                                               (float)a.nu)
+                         : transport(psi, win, p, pitch, inv2h, invh2, a.nu);
   const double wi = win[p];
   double v = a.a1 * wi;
   if (w0) v = fma(a.a0, w0[p], v);
@@ -360,17 +668,24 @@ __global__ void k_ctl_reset(PoissonCtl* c, double relax, double tol_hat, long lo
 
 // r = g(psi) - psi in FP64 on interior nodes, reduced to max |r| for the solve
 // decision; with R32 != nullptr also stored as float for the FP32 correction
-// solve, whose correction d32 then starts from zero.
+// solve, whose correction d32 then starts from zero.  Grid-stride over rows
+// with a bounded grid, so the partial-maximum array stays small.
+constexpr int kResidBlocks = 1024;
+
 __global__ __launch_bounds__(kBlock) void k_resid64(const double* __restrict__ psi,
                                                     const double* __restrict__ F,
                                                     float* __restrict__ R32,
                                                     float* __restrict__ d32, int n, int pitch,
-                                                    PoissonCtl* __restrict__ ctl) {
+                                                    PoissonCtl* __restrict__ ctl,
+                                                    double* __restrict__ part) {
   if (ctl->state != SOLVE_RUN) return;
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   double rmax = 0.0, pmax = 0.0;
-  if (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) {
+  const int m = n - 2;
+  const long long total = (long long)m * m;
+  for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < total;
+       t += (long long)gridDim.x * kBlock) {
+    const int j = 1 + (int)(t / m);
+    const int i = 1 + (int)(t - (long long)(j - 1) * m);
     const size_t p = (size_t)j * pitch + i;
     const double s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pitch] + psi[p - pitch]);
     const double sd = (psi[p + pitch + 1] + psi[p + pitch - 1]) +
@@ -381,11 +696,10 @@ __global__ __launch_bounds__(kBlock) void k_resid64(const double* __restrict__ p
       R32[p] = (float)r;
       d32[p] = 0.0f;
     }
-    rmax = mag(r);
-    pmax = mag(psi[p]);
+    rmax = fmax(rmax, mag(r));
+    pmax = fmax(pmax, mag(psi[p]));
   }
-  block_max2(rmax, pmax);
-  if (threadIdx.x == 0) finish_check(ctl, rmax, pmax, 0ll);
+  check_and_decide<kBlock>(ctl, part, rmax, pmax, 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_refine(double* __restrict__ psi,
@@ -393,7 +707,10 @@ __global__ __launch_bounds__(kBlock) void k_refine(double* __restrict__ psi,
                                                    int pitch, PoissonCtl* __restrict__ ctl,
                                                    int inner_sweeps) {
   if (ctl->state != SOLVE_RUN) return;
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ctl->sweeps += inner_sweeps;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    ctl->sweeps += inner_sweeps;
+    ctl->total_sweeps += inner_sweeps;
+  }
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i < 1 || i > n - 2 || j < 1 || j > n - 2) return;
@@ -496,6 +813,15 @@ __global__ __launch_bounds__(kBlock) void k_velocity(const double* __restrict__ 
   v[d] = -(psi[p + 1] - psi[p - 1]) * inv2h;
 }
 
+__global__ __launch_bounds__(kBlock) void k_shadow(const double* __restrict__ a,
+                                                   float* __restrict__ b, int n, int pitch) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= pitch || j >= n) return;
+  const size_t p = (size_t)j * pitch + i;
+  b[p] = (float)a[p];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fill(T* a, int n, int pitch, T value) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -531,38 +857,71 @@ inline dim3 grid2d(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); 
 // ---------------------------------------------------------------------------
 // Tile-configuration dispatch of the sweep kernels.
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TY, int S>
+template <typename T, int TX, int TY, int S, int NT>
 hipError_t sor_launch(const T* pin, T* pout, const T* F, int n, int pitch, PoissonCtl* ctl,
-                      int check, int xcd_bands, double relax, hipStream_t st) {
+                      double* part, int check, int xcd_bands, double relax, hipStream_t st) {
   const int tx = (n + TX - 1) / TX, ty = (n + TY - 1) / TY;
   const dim3 grid(tx * ty);
   if (check)
-    hipLaunchKernelGGL((k_sor<T, TX, TY, S, true>), grid, dim3(kBlock), 0, st, pin, pout, F, n,
-                       pitch, ctl, tx, xcd_bands, relax);
+    hipLaunchKernelGGL((k_sor<T, TX, TY, S, NT, true>), grid, dim3(NT), 0, st, pin, pout, F, n,
+                       pitch, ctl, part, tx, xcd_bands, relax);
   else
-    hipLaunchKernelGGL((k_sor<T, TX, TY, S, false>), grid, dim3(kBlock), 0, st, pin, pout, F, n,
-                       pitch, ctl, tx, xcd_bands, relax);
+    hipLaunchKernelGGL((k_sor<T, TX, TY, S, NT, false>), grid, dim3(NT), 0, st, pin, pout, F, n,
+                       pitch, ctl, part, tx, xcd_bands, relax);
   return hipGetLastError();
 }
 
-#define CAV_SOR_CONFIGS(X) \
-  X(64, 64, 1)             \
-  X(64, 64, 2)             \
-  X(64, 64, 3)             \
-  X(64, 32, 2)             \
-  X(32, 32, 1)             \
-  X(32, 32, 2)             \
-  X(96, 48, 2)
+// (tile x, tile y, sweeps per launch, threads per block) instantiated for FP64
+// and FP32; the autotuner chooses among them.
+#define CAV_SOR_CONFIGS_F64(X) \
+  X(32, 32, 1, 256)            \
+  X(32, 32, 2, 256)            \
+  X(64, 32, 2, 512)            \
+  X(64, 64, 1, 1024)           \
+  X(64, 64, 2, 256)            \
+  X(64, 64, 2, 1024)           \
+  X(64, 64, 3, 1024)           \
+  X(64, 64, 4, 1024)           \
+  X(128, 32, 2, 1024)          \
+  X(96, 64, 2, 1024)
+
+#define CAV_SOR_CONFIGS_F32(X) \
+  X(32, 32, 1, 256)            \
+  X(32, 32, 2, 256)            \
+  X(64, 32, 2, 512)            \
+  X(64, 64, 2, 512)            \
+  X(64, 64, 2, 1024)           \
+  X(64, 64, 4, 1024)           \
+  X(128, 64, 3, 1024)          \
+  X(128, 64, 4, 1024)          \
+  X(96, 96, 3, 1024)
 
 template <typename T>
 hipError_t sor_dispatch(const SorConfig& c, const T* pin, T* pout, const T* F, int n, int pitch,
-                        PoissonCtl* ctl, int check, double relax, hipStream_t st) {
-#define CAV_TRY(TX_, TY_, S_)                                                            \
-  if (c.tx == TX_ && c.ty == TY_ && c.s == S_)                                           \
-    return sor_launch<T, TX_, TY_, S_>(pin, pout, F, n, pitch, ctl, check, c.xcd_bands, \
-                                       relax, st);
-  CAV_SOR_CONFIGS(CAV_TRY)
-#undef CAV_TRY
+                        PoissonCtl* ctl, double* part, int check, double relax, hipStream_t st);
+
+#define CAV_TRY(TX_, TY_, S_, NT_)                                                         \
+  if (c.tx == TX_ && c.ty == TY_ && c.s == S_ && c.nt == NT_)                              \
+    return sor_launch<T, TX_, TY_, S_, NT_>(pin, pout, F, n, pitch, ctl, part, check,      \
+                                            c.xcd_bands, relax, st);
+#define CAV_HAS(TX_, TY_, S_, NT_) \
+  if (c.tx == TX_ && c.ty == TY_ && c.s == S_ && c.nt == NT_) return true;
+
+template <>
+hipError_t sor_dispatch<double>(const SorConfig& c, const double* pin, double* pout,
+                                const double* F, int n, int pitch, PoissonCtl* ctl, double* part,
+                                int check, double relax, hipStream_t st) {
+  using T = double;
+  CAV_SOR_CONFIGS_F64(CAV_TRY)
+  return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t sor_dispatch<float>(const SorConfig& c, const float* pin, float* pout, const float* F,
+                               int n, int pitch, PoissonCtl* ctl, double* part, int check,
+                               double relax, hipStream_t st) {
+  using T = float;
+  CAV_SOR_CONFIGS_F32(CAV_TRY)
   return hipErrorInvalidValue;
 }
 
@@ -586,11 +945,11 @@ hipError_t launch_poisson_rhs(const double* omega, double* F, int n, int pitch, 
   return hipGetLastError();
 }
 
-hipError_t launch_stage(const double* psi, const double* w0, const double* win, const double* wx,
-                        double* out, const double* wp, double* p_out, int n, int pitch,
-                        const StageArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_stage, grid2d(n, n), dim3(kBlock), 0, st, psi, w0, win, wx, out, wp,
-                     p_out, n, pitch, a);
+hipError_t launch_stage(const double* psi, const float* psi32, const double* w0,
+                        const double* win, const double* wx, double* out, const double* wp,
+                        double* p_out, int n, int pitch, const StageArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_stage, grid2d(n, n), dim3(kBlock), 0, st, psi, psi32, w0, win, wx, out,
+                     wp, p_out, n, pitch, a);
   return hipGetLastError();
 }
 
@@ -602,20 +961,112 @@ hipError_t launch_ctl_reset(PoissonCtl* ctl, double relax, double tol_hat, long 
 }
 
 hipError_t launch_sor64(const SorConfig& cfg, const double* psi_in, double* psi_out,
-                        const double* F, int n, int pitch, PoissonCtl* ctl, int check,
-                        hipStream_t st) {
-  return sor_dispatch<double>(cfg, psi_in, psi_out, F, n, pitch, ctl, check, 0.0, st);
+                        const double* F, int n, int pitch, PoissonCtl* ctl, double* part,
+                        int check, hipStream_t st) {
+  return sor_dispatch<double>(cfg, psi_in, psi_out, F, n, pitch, ctl, part, check, 0.0, st);
 }
 
 hipError_t launch_sor32(const SorConfig& cfg, const float* d_in, float* d_out, const float* R,
                         int n, int pitch, PoissonCtl* ctl, double relax, hipStream_t st) {
-  return sor_dispatch<float>(cfg, d_in, d_out, R, n, pitch, ctl, 0, relax, st);
+  return sor_dispatch<float>(cfg, d_in, d_out, R, n, pitch, ctl, nullptr, 0, relax, st);
 }
 
+bool sor_config_supported(const SorConfig& c, bool fp32) {
+  if (c.xcd_bands != 0 && c.xcd_bands != 1) return false;
+  if (fp32) {
+    CAV_SOR_CONFIGS_F32(CAV_HAS)
+  } else {
+    CAV_SOR_CONFIGS_F64(CAV_HAS)
+  }
+  return false;
+}
+
+int sor_max_blocks(int n) { return ((n + 31) / 32) * ((n + 31) / 32); }
+
+#define CAV_BATCH_CONFIGS_F64(X) \
+  X(32, 32, 1, 256)              \
+  X(64, 32, 2, 512)              \
+  X(64, 64, 1, 1024)             \
+  X(64, 64, 2, 1024)             \
+  X(64, 64, 3, 1024)
+
+#define CAV_BATCH_CONFIGS_F32(X) \
+  X(32, 32, 1, 256)              \
+  X(64, 32, 2, 512)              \
+  X(64, 64, 2, 1024)             \
+  X(64, 64, 4, 1024)             \
+  X(128, 64, 4, 1024)
+
+bool batch_config_supported(const SorConfig& c, bool mixed) {
+  if (c.xcd_bands != 0) return false;
+  if (mixed) {
+    CAV_BATCH_CONFIGS_F32(CAV_HAS)
+  } else {
+    CAV_BATCH_CONFIGS_F64(CAV_HAS)
+  }
+  return false;
+}
+
+template <typename K>
+int occupancy_grid(K kernel, int nt, int device) {
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess)
+    return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+int batch_grid(const SorConfig& c, bool mixed, int device) {
+#define CAV_GRID64(TX_, TY_, S_, NT_)                                    \
+  if (!mixed && c.tx == TX_ && c.ty == TY_ && c.s == S_ && c.nt == NT_) \
+    return occupancy_grid(k_batch64<TX_, TY_, S_, NT_>, NT_, device);
+#define CAV_GRID32(TX_, TY_, S_, NT_)                                   \
+  if (mixed && c.tx == TX_ && c.ty == TY_ && c.s == S_ && c.nt == NT_) \
+    return occupancy_grid(k_batch_mixed<TX_, TY_, S_, NT_>, NT_, device);
+  CAV_BATCH_CONFIGS_F64(CAV_GRID64)
+  CAV_BATCH_CONFIGS_F32(CAV_GRID32)
+#undef CAV_GRID64
+#undef CAV_GRID32
+  return 0;
+}
+
+hipError_t launch_batch64(const SorConfig& c, const BatchMember* mem, int count, int total_tiles,
+                          int pairs_per_check, BatchCtl* bc, int grid, long long spin_ticks,
+                          hipStream_t st) {
+#define CAV_L64(TX_, TY_, S_, NT_)                                                              \
+  if (c.tx == TX_ && c.ty == TY_ && c.s == S_ && c.nt == NT_) {                                 \
+    hipLaunchKernelGGL((k_batch64<TX_, TY_, S_, NT_>), dim3(grid), dim3(NT_), 0, st, mem, count, \
+                       total_tiles, pairs_per_check, bc, spin_ticks);                           \
+    return hipGetLastError();                                                                   \
+  }
+  CAV_BATCH_CONFIGS_F64(CAV_L64)
+#undef CAV_L64
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_mixed(const SorConfig& c, const BatchMember* mem, int count,
+                              int total_tiles, int inner_pairs, BatchCtl* bc, int grid,
+                              long long spin_ticks, hipStream_t st) {
+#define CAV_L32(TX_, TY_, S_, NT_)                                                          \
+  if (c.tx == TX_ && c.ty == TY_ && c.s == S_ && c.nt == NT_) {                             \
+    hipLaunchKernelGGL((k_batch_mixed<TX_, TY_, S_, NT_>), dim3(grid), dim3(NT_), 0, st, mem, \
+                       count, total_tiles, inner_pairs, bc, spin_ticks);                    \
+    return hipGetLastError();                                                               \
+  }
+  CAV_BATCH_CONFIGS_F32(CAV_L32)
+#undef CAV_L32
+  return hipErrorInvalidValue;
+}
+
+int resid_blocks() { return kResidBlocks; }
+
 hipError_t launch_resid64(const double* psi, const double* F, float* R32, float* d32, int n,
-                          int pitch, PoissonCtl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_resid64, grid2d(n, n), dim3(kBlock), 0, st, psi, F, R32, d32, n, pitch,
-                     ctl);
+                          int pitch, PoissonCtl* ctl, double* part, hipStream_t st) {
+  const long long cells = (long long)(n - 2) * (n - 2);
+  const int blocks = (int)std::min<long long>(kResidBlocks, (cells + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_resid64, dim3(blocks), dim3(kBlock), 0, st, psi, F, R32, d32, n, pitch,
+                     ctl, part);
   return hipGetLastError();
 }
 
@@ -649,6 +1100,11 @@ hipError_t launch_velocity(const double* psi, int n, int pitch, double h, double
 
 hipError_t launch_fill(double* a, int n, int pitch, double value, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<double>, grid2d(pitch, n), dim3(kBlock), 0, st, a, n, pitch, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_shadow(const double* a, float* b, int n, int pitch, hipStream_t st) {
+  hipLaunchKernelGGL(k_shadow, grid2d(pitch, n), dim3(kBlock), 0, st, a, b, n, pitch);
   return hipGetLastError();
 }
 

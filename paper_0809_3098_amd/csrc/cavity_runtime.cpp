@@ -72,13 +72,16 @@ struct Member {
   float* R32 = nullptr;
   float* d32a = nullptr;
   float* d32b = nullptr;
+  float* psi32 = nullptr;      // mixed: FP32 shadow of psi for the transport stencil
   cav::PoissonCtl* ctl = nullptr;
+  double* part = nullptr;      // per-block partial maxima of a residual check
   double* diag_partial = nullptr;
   double* diag_out = nullptr;
   int diag_np = 0;
-  cav::SorConfig cfg64{64, 64, 2, 0};
-  cav::SorConfig cfg32{64, 64, 2, 0};
-  int inner_sweeps = 0;  // mixed: FP32 sweeps per refinement round
+  cav::SorConfig cfg64{64, 64, 2, 1024, 0};
+  cav::SorConfig cfg32{64, 64, 2, 1024, 0};
+  int pairs_per_check = 1;  // FP64: launch pairs between residual checks
+  int inner_sweeps = 0;     // mixed: FP32 sweeps per refinement round
   // host-side state
   long long step = 0;
   double t = 0;
@@ -113,6 +116,15 @@ namespace {
   } while (0)
 
 int pitch_of(int n) { return (n + 31) / 32 * 32; }
+
+// Residual-check spacing (FP64) and inner sweeps per refinement round
+// (mixed), rounded to whole launch pairs of the current kernels.
+void set_schedule(Member& m, int check_every, int inner) {
+  const int u64 = 2 * m.cfg64.s;
+  m.pairs_per_check = std::max(1, (check_every + u64 - 1) / u64);
+  const int u32 = 2 * m.cfg32.s;
+  m.inner_sweeps = std::max(u32, (inner + u32 - 1) / u32 * u32);
+}
 
 // Validation and derived quantities (Sec. 3.2: Re = |U| L / nu, L = 1).
 int derive(const cavity_params& p, Member& m) {
@@ -156,29 +168,33 @@ int derive(const cavity_params& p, Member& m) {
   // residual halvings' worth of sweeps (about 0.11 (n-1) each) before polishing.
   m.stall_window = std::max<long long>(64, 2LL * p.n);
   // tiles: small grids favour more, smaller blocks
+  // (measured on MI355X: 64x64 tiles with 4 sweeps per launch and 1024
+  // threads are fastest from 1024^2 up; XCD-banded tile order helps while the
+  // tile count is a multiple of 8)
   if (p.n <= 320) {
-    m.cfg64 = {32, 32, 1, 0};
-    m.cfg32 = {32, 32, 1, 0};
+    m.cfg64 = {32, 32, 1, 256, 0};
+    m.cfg32 = {32, 32, 1, 256, 0};
   } else {
-    m.cfg64 = {64, 64, 2, 0};
-    m.cfg32 = {64, 64, 2, 0};
+    const int tiles = ((p.n + 63) / 64) * ((p.n + 63) / 64);
+    const int xcd = (tiles % 8 == 0 && p.n <= 2048) ? 1 : 0;
+    m.cfg64 = {64, 64, 4, 1024, xcd};
+    m.cfg32 = {64, 64, 4, 1024, xcd};
   }
-  // Mixed precision: FP32 sweeps per refinement round, enough for about
-  // three decades of residual reduction of the correction.
-  {
-    const int unit = 2 * m.cfg32.s;
-    const int want = (int)std::ceil(1.5 * (p.n - 1));
-    m.inner_sweeps = std::max(unit, (want + unit - 1) / unit * unit);
-  }
+  set_schedule(m, std::min(32, std::max(4, p.n / 32)), (int)std::ceil(1.5 * (p.n - 1)));
   return CAVITY_OK;
+}
+
+size_t part_doubles(int n) {
+  return 2 * (size_t)std::max(cav::sor_max_blocks(n), cav::resid_blocks());
 }
 
 size_t member_bytes(const Member& m) {
   const size_t f64 = align_up((size_t)m.n * m.pitch * sizeof(double));
   const size_t f32 = align_up((size_t)m.n * m.pitch * sizeof(float));
   size_t b = 8 * f64;  // w[4], psi, psi_b, psi_prev, F
-  if (m.mixed) b += 3 * f32;
+  if (m.mixed) b += 4 * f32;
   b += align_up(sizeof(cav::PoissonCtl));
+  b += align_up(part_doubles(m.n) * sizeof(double));
   b += align_up((size_t)cav::diag_partials(m.n) * 4 * sizeof(double));
   b += align_up(4 * sizeof(double));
   return b;
@@ -201,8 +217,10 @@ void carve(Member& m, char*& cur) {
     m.R32 = reinterpret_cast<float*>(take(f32));
     m.d32a = reinterpret_cast<float*>(take(f32));
     m.d32b = reinterpret_cast<float*>(take(f32));
+    m.psi32 = reinterpret_cast<float*>(take(f32));
   }
   m.ctl = reinterpret_cast<cav::PoissonCtl*>(take(align_up(sizeof(cav::PoissonCtl))));
+  m.part = reinterpret_cast<double*>(take(align_up(part_doubles(m.n) * sizeof(double))));
   m.diag_np = cav::diag_partials(m.n);
   m.diag_partial = reinterpret_cast<double*>(take(align_up((size_t)m.diag_np * 4 * 8)));
   m.diag_out = reinterpret_cast<double*>(take(align_up(4 * sizeof(double))));
@@ -216,21 +234,33 @@ void carve(Member& m, char*& cur) {
 // ---------------------------------------------------------------------------
 int reset_ctl(cavity_s* h, Member& m) {
   const double tol_hat = m.tol * 0.3 * m.h * m.h;  // (g - psi) = (3 h^2 / 10) r
-  const long long spc = m.mixed ? m.inner_sweeps : 2LL * m.cfg64.s;
+  const long long spc = m.mixed ? m.inner_sweeps : 2LL * m.cfg64.s * m.pairs_per_check;
   HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, m.stall_window, spc,
                                    h->st));
   return CAVITY_OK;
 }
 
-// One chunk of work for member m: `units` sweep pairs (FP64) or refinement
-// rounds (mixed).  Every launch returns at once once the solve has stopped.
+// Sweeps between two residual checks.
+long long unit_sweeps(const Member& m) {
+  return m.mixed ? m.inner_sweeps : 2LL * m.cfg64.s * m.pairs_per_check;
+}
+
+// One chunk of work for member m: `units` check groups (FP64: pairs_per_check
+// launch pairs, the last launch checking) or refinement rounds (mixed).
+// Every launch returns at once once the solve has stopped.
 int enqueue_chunk(cavity_s* h, Member& m, int units) {
   for (int u = 0; u < units; ++u) {
     if (!m.mixed) {
-      HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi, m.psi_b, m.F, m.n, m.pitch, m.ctl, 0, h->st));
-      HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi_b, m.psi, m.F, m.n, m.pitch, m.ctl, 1, h->st));
+      for (int q = 0; q < m.pairs_per_check; ++q) {
+        const int check = (q == m.pairs_per_check - 1) ? 1 : 0;
+        HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi, m.psi_b, m.F, m.n, m.pitch, m.ctl, m.part,
+                                     0, h->st));
+        HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi_b, m.psi, m.F, m.n, m.pitch, m.ctl, m.part,
+                                     check, h->st));
+      }
     } else {
-      HIP_TRY(h, cav::launch_resid64(m.psi, m.F, m.R32, m.d32a, m.n, m.pitch, m.ctl, h->st));
+      HIP_TRY(h, cav::launch_resid64(m.psi, m.F, m.R32, m.d32a, m.n, m.pitch, m.ctl, m.part,
+                                     h->st));
       const int pairs = m.inner_sweeps / (2 * m.cfg32.s);
       for (int q = 0; q < pairs; ++q) {
         // the last pair relaxes with 1 (Gauss-Seidel) to damp the FP32
@@ -251,7 +281,8 @@ int enqueue_chunk(cavity_s* h, Member& m, int units) {
 // then needs no sweep at all.
 int enqueue_initial_check(cavity_s* h, Member& m) {
   if (m.mixed) return CAVITY_OK;  // the first refinement round starts with a check
-  HIP_TRY(h, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, h->st));
+  HIP_TRY(h, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, m.part,
+                                 h->st));
   return CAVITY_OK;
 }
 
@@ -276,7 +307,7 @@ int solve_members(cavity_s* h, const std::vector<int>& idx) {
   while (!active.empty()) {
     for (int k : active) {
       Member& m = h->m[k];
-      const long long per_unit = m.mixed ? m.inner_sweeps : 2LL * m.cfg64.s;
+      const long long per_unit = unit_sweeps(m);
       long long units;
       if (first && m.est_sweeps > 0)
         units = (long long)std::ceil(1.05 * m.est_sweeps / per_unit);
@@ -295,7 +326,7 @@ int solve_members(cavity_s* h, const std::vector<int>& idx) {
       const cav::PoissonCtl& c = h->host_ctl[k];
       if (c.state != cav::SOLVE_RUN) continue;
       Member& m = h->m[k];
-      const long long per_unit = m.mixed ? m.inner_sweeps : 2LL * m.cfg64.s;
+      const long long per_unit = unit_sweeps(m);
       if (enqueued[k] * per_unit > 2 * m.max_sweeps + 64 * per_unit) {
         // the device never stopped the solve: a defect, not a slow solve
         h->poisoned = true;
@@ -305,6 +336,10 @@ int solve_members(cavity_s* h, const std::vector<int>& idx) {
       still.push_back(k);
     }
     active.swap(still);
+  }
+  for (int k : idx) {
+    Member& m = h->m[k];
+    if (m.mixed) HIP_TRY(h, cav::launch_shadow(m.psi, m.psi32, m.n, m.pitch, h->st));
   }
   int worst = CAVITY_OK;
   for (int k : idx) {
@@ -379,7 +414,8 @@ int step_all(cavity_s* h, bool want_diag) {
           win = m.w[3]; wx = m.w[2]; out = m.w[1]; a.a1 = kA54; a.ax = 1.0; a.b = kB54 * dt;
           break;
       }
-      HIP_TRY(h, cav::launch_stage(m.psi, w0, win, wx, out, wp, pout, m.n, m.pitch, a, h->st));
+      HIP_TRY(h, cav::launch_stage(m.psi, m.mixed ? m.psi32 : nullptr, w0, win, wx, out, wp, pout,
+                                   m.n, m.pitch, a, h->st));
       if ((rc = enqueue_rhs_and_walls_prep(h, m, out)) != CAVITY_OK) return rc;
     }
     rc = solve_members(h, all);
@@ -474,7 +510,7 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
       if (cav::launch_fill(f, m.n, m.pitch, 0.0, h->st) != hipSuccess)
         return bail(fail(CAVITY_EHIP, "fill failed"));
     if (m.mixed) {
-      float* f32[] = {m.R32, m.d32a, m.d32b};
+      float* f32[] = {m.R32, m.d32a, m.d32b, m.psi32};
       for (float* f : f32)
         if (cav::launch_fill32(f, m.n, m.pitch, 0.0f, h->st) != hipSuccess)
           return bail(fail(CAVITY_EHIP, "fill failed"));
@@ -503,6 +539,10 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
     if (cav::launch_thom(m.psi, m.w[0], m.n, m.pitch, m.h, m.u_lid, h->st) != hipSuccess)
       return bail(fail(CAVITY_EHIP, "thom failed"));
   }
+  for (Member& m : h->m)
+    if (m.mixed && m.p.resume &&
+        cav::launch_shadow(m.psi, m.psi32, m.n, m.pitch, h->st) != hipSuccess)
+      return bail(fail(CAVITY_EHIP, "shadow failed"));
   if (hipStreamSynchronize(h->st) != hipSuccess) return bail(fail(CAVITY_EHIP, "sync failed"));
   for (Member& m : h->m) {
     m.sweeps_total = 0;
@@ -612,29 +652,90 @@ int cavity_fields(cavity_t h, int32_t idx, double* d_psi, double* d_omega, doubl
   return CAVITY_OK;
 }
 
-int cavity_relax(cavity_t h, int32_t idx, int32_t sweeps, double* d_psi_out, int64_t* done) {
+int cavity_relax(cavity_t h, int32_t idx, int32_t sweeps, int32_t arith, double* d_psi_out,
+                 int64_t* done) {
   if (!h) return fail(CAVITY_EINVAL, "null handle");
   if (h->poisoned) return fail(CAVITY_ESTATE, "handle poisoned by an earlier failure");
   if (idx < 0 || idx >= h->count) return fail(CAVITY_EINVAL, "idx %d out of range", idx);
   if (sweeps < 0) return fail(CAVITY_EINVAL, "sweeps must be >= 0");
-  HIP_TRY(h, hipSetDevice(h->device));
+  if (arith != 0 && arith != 1) return fail(CAVITY_EINVAL, "arith must be 0 or 1");
   Member& m = h->m[idx];
+  if (arith == 1 && (!m.mixed || d_psi_out))
+    return fail(CAVITY_EINVAL, "arith 1 needs a CAVITY_MIXED cavity and no psi output");
+  HIP_TRY(h, hipSetDevice(h->device));
   // Scratch: psi_prev / psi_b hold the iterate, F the right-hand side.  The
   // control block is reset with an unreachable tolerance so that no launch
   // returns early.
-  HIP_TRY(h, cav::launch_copy(m.psi, m.psi_prev, m.n, m.pitch, h->st));
   HIP_TRY(h, cav::launch_poisson_rhs(m.w[0], m.F, m.n, m.pitch, m.h, h->st));
   HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, -1.0, 1LL << 62, 1LL << 62, 0, h->st));
-  const int per = m.cfg64.s;
+  const int per = arith ? m.cfg32.s : m.cfg64.s;
   const int launches = (sweeps + 2 * per - 1) / (2 * per) * 2;
-  for (int k = 0; k < launches; k += 2) {
-    HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi_prev, m.psi_b, m.F, m.n, m.pitch, m.ctl, 0,
-                                 h->st));
-    HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi_b, m.psi_prev, m.F, m.n, m.pitch, m.ctl, 0,
-                                 h->st));
+  if (arith == 0) {
+    HIP_TRY(h, cav::launch_copy(m.psi, m.psi_prev, m.n, m.pitch, h->st));
+    for (int k = 0; k < launches; k += 2) {
+      HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi_prev, m.psi_b, m.F, m.n, m.pitch, m.ctl,
+                                   m.part, 0, h->st));
+      HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi_b, m.psi_prev, m.F, m.n, m.pitch, m.ctl,
+                                   m.part, 0, h->st));
+    }
+    if (d_psi_out) HIP_TRY(h, cav::launch_copy_out(m.psi_prev, d_psi_out, m.n, m.pitch, h->st));
+  } else {
+    HIP_TRY(h, cav::launch_resid64(m.psi, m.F, m.R32, m.d32a, m.n, m.pitch, m.ctl, m.part,
+                                   h->st));
+    HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, -1.0, 1LL << 62, 1LL << 62, 0, h->st));
+    for (int k = 0; k < launches; k += 2) {
+      HIP_TRY(h, cav::launch_sor32(m.cfg32, m.d32a, m.d32b, m.R32, m.n, m.pitch, m.ctl, m.relax,
+                                   h->st));
+      HIP_TRY(h, cav::launch_sor32(m.cfg32, m.d32b, m.d32a, m.R32, m.n, m.pitch, m.ctl, m.relax,
+                                   h->st));
+    }
   }
-  if (d_psi_out) HIP_TRY(h, cav::launch_copy_out(m.psi_prev, d_psi_out, m.n, m.pitch, h->st));
   if (done) *done = (int64_t)launches * per;
+  return CAVITY_OK;
+}
+
+int cavity_get_tuning(cavity_t h, int32_t idx, cavity_tuning* t) {
+  if (!h || !t) return fail(CAVITY_EINVAL, "null argument");
+  if (idx < 0 || idx >= h->count) return fail(CAVITY_EINVAL, "idx %d out of range", idx);
+  const Member& m = h->m[idx];
+  std::memset(t, 0, sizeof *t);
+  t->tile_x = m.cfg64.tx;
+  t->tile_y = m.cfg64.ty;
+  t->sweeps_per_launch = m.cfg64.s;
+  t->threads = m.cfg64.nt;
+  t->tile_x32 = m.cfg32.tx;
+  t->tile_y32 = m.cfg32.ty;
+  t->sweeps_per_launch32 = m.cfg32.s;
+  t->threads32 = m.cfg32.nt;
+  t->check_every = (int32_t)(2LL * m.cfg64.s * m.pairs_per_check);
+  t->inner_sweeps = m.inner_sweeps;
+  t->xcd_bands = m.cfg64.xcd_bands;
+  t->sor_omega = m.relax;
+  return CAVITY_OK;
+}
+
+int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t) {
+  if (!h || !t) return fail(CAVITY_EINVAL, "null argument");
+  if (idx < 0 || idx >= h->count) return fail(CAVITY_EINVAL, "idx %d out of range", idx);
+  const cav::SorConfig c64{t->tile_x, t->tile_y, t->sweeps_per_launch, t->threads, t->xcd_bands};
+  const cav::SorConfig c32{t->tile_x32, t->tile_y32, t->sweeps_per_launch32, t->threads32,
+                           t->xcd_bands};
+  if (!cav::sor_config_supported(c64, false))
+    return fail(CAVITY_EINVAL, "FP64 sweep kernel %dx%d s=%d nt=%d xcd=%d is not compiled",
+                c64.tx, c64.ty, c64.s, c64.nt, c64.xcd_bands);
+  if (!cav::sor_config_supported(c32, true))
+    return fail(CAVITY_EINVAL, "FP32 sweep kernel %dx%d s=%d nt=%d xcd=%d is not compiled",
+                c32.tx, c32.ty, c32.s, c32.nt, c32.xcd_bands);
+  if (t->check_every < 1 || t->inner_sweeps < 1)
+    return fail(CAVITY_EINVAL, "check_every and inner_sweeps must be >= 1");
+  if (!(t->sor_omega > 0.0 && t->sor_omega < 2.0))
+    return fail(CAVITY_EINVAL, "sor_omega must lie in (0, 2)");
+  Member& m = h->m[idx];
+  m.cfg64 = c64;
+  m.cfg32 = c32;
+  m.relax = t->sor_omega;
+  set_schedule(m, t->check_every, t->inner_sweeps);
+  m.est_sweeps = 0;
   return CAVITY_OK;
 }
 

@@ -42,6 +42,8 @@ def test_fixed_sweeps_match_oracle_four_colour_sweeps(cav_mod, n, sweeps):
     omega = inputs.random_field(n, seed=100 + n)
     c = cav_mod.Cavity(cav_mod.Params(n=n, re=1000.0, sor_omega=relax,
                                       poisson_max_sweeps=sweeps))
+    # check after every launch pair, so the sweep limit stops at `sweeps`
+    c.set_tuning(check_every=2 * c.tuning()["sweeps_per_launch"])
     psi, info = c.poisson(0, omega, allow_noconv=True)
     c.close()
     assert info["sweeps"] == sweeps
