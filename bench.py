@@ -1,12 +1,16 @@
 """Throughput of the driven-lid-cavity time step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--exec stream|persistent|graph] [--no-cpu] [--no-extras]
 
 A step is one SSPRK(5,4) step of the whole hot path (five stages, each with
 transport RHS + stage combination, compact-Poisson SOR solve to tolerance,
-Thom walls) on the synthetic workload: the 1024 x 1024 cavity at Re = 1e4,
-started from rest, FP64, Poisson tolerance 1e-10.  Inputs are resident in
-HBM when timing starts.  Prints one JSON line.
+Thom walls).  The headline workload is the 1024 x 1024 cavity at Re = 1e4,
+started from rest, FP64, Poisson tolerance 1e-10.  Inputs are resident in HBM
+when timing starts.  Extras (same JSON line): the mixed-precision 1024 x 1024
+Re = 3e4 cavity, and the six-cavity Reynolds sweep (256^2 ... 1024^2) batched
+in one persistent launch per stage vs the same cavities run one by one.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -23,8 +27,9 @@ if ROOT not in sys.path:
 
 METRIC = "Mcell-steps/s at 1024² (FP64 vs mixed+refine), achieved HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_SWEEP_CELL = {0: 24.0, 1: 12.0}   # FP64 / FP32 algorithmic bytes per node per sweep
+BYTES_PER_SWEEP_NODE = {0: 24.0, 1: 12.0}   # FP64 / FP32: psi in, rhs in, psi out
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sor_traffic.json")
+EXEC = {"stream": 0, "persistent": 1, "graph": 2}
 
 
 def _kernel_source_hash() -> str:
@@ -33,11 +38,11 @@ def _kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(workload: str):
+def _traffic(key: str):
     """HBM bytes per sweep launch from committed PMC counters, if still valid."""
     try:
         with open(TRAFFIC_FILE) as f:
-            rec = json.load(f).get(workload)
+            rec = json.load(f).get(key)
     except (OSError, ValueError):
         return None
     if not rec or rec.get("kernel_source_sha256_16") != _kernel_source_hash():
@@ -46,99 +51,145 @@ def _traffic(workload: str):
 
 
 def _cpu_baseline(n, re, steps):
-    import numpy as np  # noqa: F401
     from oracle.cavity_oracle import CavityOracle
     cores = os.cpu_count() or 1
     o = CavityOracle(n, re, workers=cores)
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": n * n * steps / dt / 1e6, "unit": "Mcell-steps/s", "cores": cores,
+    return {"value": round(n * n * steps / dt / 1e6, 4), "unit": "Mcell-steps/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{steps} steps of the {n}x{n} Re={re:g} cavity from rest; exact DST "
                       f"Poisson per stage (scipy.fft workers={cores}), NumPy elementwise on 1 "
                       f"thread; {dt:.1f} s"}
 
 
+def _timed_steps(torch, cav, steps, warmup):
+    dev = torch.device("cuda:0")
+    if warmup:
+        cav.step(warmup, want_stats=False)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    stats = cav.step(steps, want_stats=True) if steps else None
+    torch.cuda.synchronize(dev)
+    return time.perf_counter() - t0, stats
+
+
+def _sweep_roofline(torch, cav, stream, launches, arith, key):
+    """Average launch duration of the sweep kernel, event-timed on its stream."""
+    tun = cav.tuning(0)
+    s = tun["sweeps_per_launch32"] if arith else tun["sweeps_per_launch"]
+    n = cav.params[0].n
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    cav.relax(2 * s, arith=arith)  # warm the scratch buffers
+    ev0.record(stream)
+    done, _ = cav.relax(launches * s, arith=arith)
+    ev1.record(stream)
+    ev1.synchronize()
+    per_launch_s = ev0.elapsed_time(ev1) / 1e3 / (done // s)
+    alg = BYTES_PER_SWEEP_NODE[arith] * (n - 2) ** 2 * s
+    achieved = alg / per_launch_s / 1e9
+    if arith:
+        kern = f"k_sor<float,{tun['tile_x32']},{tun['tile_y32']},{s},{tun['threads32']}>"
+    else:
+        kern = f"k_sor<double,{tun['tile_x']},{tun['tile_y']},{s},{tun['threads']}>"
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(key), "kernel": kern,
+            "alg_bytes_per_launch": alg, "avg_launch_us": round(per_launch_s * 1e6, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cavity1024_re1e4_fp64")
+    ap.add_argument("--exec", default="persistent", choices=sorted(EXEC))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip mixed and batched lines")
     ap.add_argument("--cpu-steps", type=int, default=8)
-    ap.add_argument("--relax-launches", type=int, default=400)
+    ap.add_argument("--relax-launches", type=int, default=200)
+    ap.add_argument("--extra-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the batched and "
-              f"single-cavity paths are single-GPU designs.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): every workload here is "
+              f"measured on a single MI355X.", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_0809_3098_amd.cavity import CAVITY_FP64, CAVITY_MIXED, Cavity, Params
     from paper_0809_3098_amd.workloads import WORKLOADS
 
-    wl = WORKLOADS[args.workload]
-    n, re, tol = wl["n"], wl["re"], wl["tol"]
-    prec = CAVITY_MIXED if wl["precision"] == "mixed" else CAVITY_FP64
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    cav = Cavity(Params(n=n, re=re, poisson_tol=tol, precision=prec), device="cuda:0",
-                 stream=stream)
-    if args.warmup:
-        cav.step(args.warmup, want_stats=False)
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    stats = cav.step(args.steps, want_stats=True)[0] if args.steps else None
-    torch.cuda.synchronize(dev)
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / max(args.steps, 1)
-    value = n * n * args.steps / elapsed / 1e6 if args.steps else 0.0
 
-    # Dominant kernel: the temporally blocked SOR sweep.  Average launch
-    # duration from events on the kernel's stream around back-to-back launches.
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    cav.relax(2)  # warm the scratch buffers
-    ev0.record(stream)
-    done, _ = cav.relax(args.relax_launches * 2)  # sweeps; rounded to whole launches
-    ev1.record(stream)
-    ev1.synchronize()
-    relax_ms = ev0.elapsed_time(ev1)
-    tun = cav.tuning(0)
-    sweeps_per_launch = tun["sweeps_per_launch"]
-    launches = done // sweeps_per_launch
-    per_launch_s = relax_ms / 1e3 / launches
-    cells = (n - 2) ** 2
-    alg_bytes = BYTES_PER_SWEEP_CELL[0] * cells * sweeps_per_launch
-    achieved = alg_bytes / per_launch_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": _traffic(args.workload),
-                "kernel": (f"k_sor<double,{tun['tile_x']},{tun['tile_y']},"
-                           f"{sweeps_per_launch},{tun['threads']}>"),
-                "alg_bytes_per_launch": alg_bytes,
-                "avg_launch_us": round(per_launch_s * 1e6, 3)}
+    def single(name, steps, warmup, mode):
+        wl = WORKLOADS[name]
+        prec = CAVITY_MIXED if wl["precision"] == "mixed" else CAVITY_FP64
+        cav = Cavity(Params(n=wl["n"], re=wl["re"], poisson_tol=wl["tol"], precision=prec),
+                     device="cuda:0", stream=stream)
+        cav.set_exec(EXEC[mode])
+        el, stats = _timed_steps(torch, cav, steps, warmup)
+        n = wl["n"]
+        out = {"value": round(n * n * steps / el / 1e6, 4) if steps else 0.0,
+               "ms_per_step": round(1e3 * el / max(steps, 1), 3),
+               "sweeps_per_stage": stats[0]["sweeps_last_step"] / 5 if stats else None,
+               "floor_limited_last_step": stats[0]["floor_limited"] if stats else None,
+               "exec": mode}
+        return cav, prec, out
+
+    # ---- headline: FP64 1024^2
+    cav, prec, head = single(args.workload, args.steps, args.warmup, args.exec)
+    wl = WORKLOADS[args.workload]
+    n = wl["n"]
+    roofline = _sweep_roofline(torch, cav, stream, args.relax_launches, 0,
+                               f"{args.workload}:fp64")
     cav.close()
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = _cpu_baseline(n, re, args.cpu_steps)
+    extras = {}
+    if not args.no_extras:
+        # mixed + refinement at 1024^2, Re 3e4
+        cavm, _, mixed = single("cavity1024_re3e4_mixed", args.extra_steps, 1, args.exec)
+        mixed["roofline_fp32_sweep"] = _sweep_roofline(torch, cavm, stream, args.relax_launches,
+                                                       1, "cavity1024_re3e4_mixed:fp32")
+        cavm.close()
+        extras["mixed_1024_re3e4"] = mixed
+        # batched six-cavity Reynolds sweep vs one by one
+        b = WORKLOADS["re_sweep6"]
+        cells = sum(m * m for _, m in b["members"])
+        for label, prec_b in (("fp64", CAVITY_FP64), ("mixed", CAVITY_MIXED)):
+            cb = Cavity([Params(n=m, re=r, poisson_tol=b["tol"], precision=prec_b)
+                         for r, m in b["members"]], device="cuda:0", stream=stream)
+            el, _ = _timed_steps(torch, cb, args.extra_steps, 1)
+            cb.close()
+            seq = 0.0
+            for r, m in b["members"]:
+                cs = Cavity(Params(n=m, re=r, poisson_tol=b["tol"], precision=prec_b),
+                            device="cuda:0", stream=stream)
+                e1, _ = _timed_steps(torch, cs, args.extra_steps, 1)
+                seq += e1
+                cs.close()
+            extras[f"re_sweep6_{label}"] = {
+                "cells": cells,
+                "batched_graph_mcell_steps_s": round(cells * args.extra_steps / el / 1e6, 4),
+                "sequential_stream_mcell_steps_s": round(cells * args.extra_steps / seq / 1e6, 4),
+                "speedup": round(seq / el, 3), "steps": args.extra_steps}
 
+    cpu = None if args.no_cpu else _cpu_baseline(n, wl["re"], args.cpu_steps)
     line = {
-        "metric": METRIC, "value": round(value, 4), "unit": "Mcell-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "metric": METRIC, "value": head["value"], "unit": "Mcell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == CAVITY_FP64 else "f32+f64", "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "re": re, "poisson_tol": tol,
-                   "precision": wl["precision"], "init": wl["init"],
-                   "sweeps_per_step": stats["sweeps_last_step"] if stats else None,
-                   "sweeps_per_stage": stats["sweeps_last_step"] / 5 if stats else None,
-                   "floor_limited_last_step": stats["floor_limited"] if stats else None},
+        "config": {"workload": args.workload, "n": n, "re": wl["re"], "poisson_tol": wl["tol"],
+                   "precision": wl["precision"], "init": wl["init"], "exec": head["exec"],
+                   "sweeps_per_stage": head["sweeps_per_stage"],
+                   "floor_limited_last_step": head["floor_limited_last_step"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(line), flush=True)
 

@@ -208,9 +208,34 @@ typedef struct cavity_tuning {
   double sor_omega;              /* relaxation parameter in (0, 2)                 */
 } cavity_tuning;
 
-/* Read / replace the launch configuration of cavity idx (host only). */
+/*
+ * Read / replace the launch configuration of cavity idx (host only).  idx = -1
+ * addresses the batched persistent kernel shared by every cavity of the handle
+ * (its sor_omega and xcd_bands are unused; each cavity keeps its own
+ * relaxation parameter).  Replacing a configuration discards captured graphs.
+ */
 int cavity_get_tuning(cavity_t h, int32_t idx, cavity_tuning* t);
 int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t);
+
+/*
+ * How cavity_step runs the Poisson solves.
+ *   CAVITY_EXEC_STREAM      one launch per S sweeps, every cavity on its own;
+ *                           the host reads each solve's decision once per chunk
+ *                           of enqueued launches (default for one cavity).
+ *   CAVITY_EXEC_PERSISTENT  one persistent launch per stage solves every cavity
+ *                           of the handle (tile list over all cavities, grid
+ *                           barriers between sweep rounds, per-cavity stopping
+ *                           decisions on the device); one readback per step.
+ *   CAVITY_EXEC_GRAPH       as PERSISTENT, with the whole step (five stages)
+ *                           captured once per buffer parity in a hipGraph and
+ *                           replayed (default for count > 1).
+ * Both persistent modes need one precision for all cavities (EINVAL
+ * otherwise).  With the same tile sweeps per launch, check spacing and
+ * relaxation, all three modes give bitwise identical results.
+ */
+enum cavity_exec { CAVITY_EXEC_STREAM = 0, CAVITY_EXEC_PERSISTENT = 1, CAVITY_EXEC_GRAPH = 2 };
+int cavity_set_exec(cavity_t h, int32_t mode);
+int cavity_get_exec(cavity_t h, int32_t* mode);
 
 /* Release the handle (host memory only; the workspace stays the caller's). */
 int cavity_destroy(cavity_t h);

@@ -33,6 +33,9 @@ CAVITY_ENONFINITE = -5
 CAVITY_ESTATE = -6
 CAVITY_FP64 = 0
 CAVITY_MIXED = 1
+CAVITY_EXEC_STREAM = 0
+CAVITY_EXEC_PERSISTENT = 1
+CAVITY_EXEC_GRAPH = 2
 
 _STATUS_NAMES = {0: "CAVITY_OK", -1: "CAVITY_EINVAL", -2: "CAVITY_ENOMEM", -3: "CAVITY_EHIP",
                  -4: "CAVITY_ENOCONV", -5: "CAVITY_ENONFINITE", -6: "CAVITY_ESTATE"}
@@ -107,16 +110,18 @@ _lib.cavity_relax.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, c
                               ctypes.c_void_p, _P(ctypes.c_int64)]
 _lib.cavity_get_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(cavity_tuning)]
 _lib.cavity_set_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(cavity_tuning)]
+_lib.cavity_set_exec.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+_lib.cavity_get_exec.argtypes = [ctypes.c_void_p, _P(ctypes.c_int32)]
 _lib.cavity_destroy.argtypes = [ctypes.c_void_p]
 _lib.cavity_last_error.restype = ctypes.c_char_p
 for _f in ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_poisson",
            "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
-           "cavity_destroy"):
+           "cavity_set_exec", "cavity_get_exec", "cavity_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_poisson",
             "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
-            "cavity_destroy", "cavity_last_error")
+            "cavity_set_exec", "cavity_get_exec", "cavity_destroy", "cavity_last_error")
 
 
 def cavity_last_error() -> str:
@@ -227,6 +232,16 @@ def cavity_set_tuning(h: int, idx: int, **kw) -> dict:
     return cavity_get_tuning(h, idx)
 
 
+def cavity_set_exec(h: int, mode: int) -> None:
+    _check(_lib.cavity_set_exec(ctypes.c_void_p(h), mode))
+
+
+def cavity_get_exec(h: int) -> int:
+    out = ctypes.c_int32(0)
+    _check(_lib.cavity_get_exec(ctypes.c_void_p(h), ctypes.byref(out)))
+    return int(out.value)
+
+
 def cavity_destroy(h: int) -> None:
     _check(_lib.cavity_destroy(ctypes.c_void_p(h)))
 
@@ -316,6 +331,12 @@ class Cavity:
 
     def set_tuning(self, idx: int = 0, **kw) -> dict:
         return cavity_set_tuning(self.handle, idx, **kw)
+
+    def set_exec(self, mode: int) -> None:
+        cavity_set_exec(self.handle, mode)
+
+    def exec_mode(self) -> int:
+        return cavity_get_exec(self.handle)
 
     def close(self):
         if getattr(self, "handle", 0):

@@ -168,6 +168,8 @@ hipError_t launch_velocity(const double* psi, int n, int pitch, double h, double
 // Pitched <-> dense copies and fills.
 hipError_t launch_fill(double* a, int n, int pitch, double value, hipStream_t st);
 hipError_t launch_fill32(float* a, int n, int pitch, float value, hipStream_t st);
+// Zero `bytes` (a multiple of 4) with a kernel (graph-safe, unlike memset).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 // b = (float)a over the whole pitched array.
 hipError_t launch_shadow(const double* a, float* b, int n, int pitch, hipStream_t st);
 hipError_t launch_copy_in(const double* dense, double* pitched, int n, int pitch,

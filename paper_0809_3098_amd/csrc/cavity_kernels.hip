@@ -813,6 +813,12 @@ __global__ __launch_bounds__(kBlock) void k_velocity(const double* __restrict__ 
   v[d] = -(psi[p + 1] - psi[p - 1]) * inv2h;
 }
 
+__global__ __launch_bounds__(kBlock) void k_zero(unsigned int* p, size_t words) {
+  for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < words;
+       k += (size_t)gridDim.x * kBlock)
+    p[k] = 0u;
+}
+
 __global__ __launch_bounds__(kBlock) void k_shadow(const double* __restrict__ a,
                                                    float* __restrict__ b, int n, int pitch) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -988,7 +994,8 @@ int sor_max_blocks(int n) { return ((n + 31) / 32) * ((n + 31) / 32); }
   X(64, 32, 2, 512)              \
   X(64, 64, 1, 1024)             \
   X(64, 64, 2, 1024)             \
-  X(64, 64, 3, 1024)
+  X(64, 64, 3, 1024)             \
+  X(64, 64, 4, 1024)
 
 #define CAV_BATCH_CONFIGS_F32(X) \
   X(32, 32, 1, 256)              \
@@ -1100,6 +1107,15 @@ hipError_t launch_velocity(const double* psi, int n, int pitch, double h, double
 
 hipError_t launch_fill(double* a, int n, int pitch, double value, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<double>, grid2d(pitch, n), dim3(kBlock), 0, st, a, n, pitch, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t words = bytes / 4;
+  const int blocks = (int)std::min<size_t>(1024, (words + kBlock - 1) / kBlock);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(kBlock), 0, st, static_cast<unsigned int*>(p),
+                     words);
   return hipGetLastError();
 }
 

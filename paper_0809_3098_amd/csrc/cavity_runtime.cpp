@@ -102,6 +102,24 @@ struct cavity_s {
   std::vector<Member> m;
   cav::PoissonCtl* host_ctl = nullptr;  // pinned readback of every member's ctl
   double* host_diag = nullptr;          // pinned readback, 4 per member
+  // ---- execution of the Poisson solves
+  int exec = CAVITY_EXEC_STREAM;
+  bool mixed = false;                   // batch precision (all members agree)
+  cav::SorConfig bcfg64{64, 64, 4, 1024, 0};
+  cav::SorConfig bcfg32{64, 64, 4, 1024, 0};
+  int b_ppc = 1;                        // FP64: launch-pairs per check
+  int b_inner_pairs = 1;                // mixed: FP32 launch-pairs per round
+  int total_tiles = 0;
+  int grid = 0;
+  cav::BatchMember* d_mem = nullptr;    // device descriptors (workspace)
+  cav::BatchCtl* d_bc = nullptr;        // grid barrier (workspace)
+  cav::BatchCtl* host_bc = nullptr;     // pinned readback
+  std::vector<cav::BatchMember> h_mem;
+  std::vector<cav::PoissonCtl> last_tot;  // totals at the previous readback
+  double* w0_base = nullptr;            // member 0's initial w[0]: step parity
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipStream_t cap_st = nullptr;         // private stream graphs are recorded on
 };
 
 namespace {
@@ -186,6 +204,10 @@ int derive(const cavity_params& p, Member& m) {
 
 size_t part_doubles(int n) {
   return 2 * (size_t)std::max(cav::sor_max_blocks(n), cav::resid_blocks());
+}
+
+size_t handle_bytes(int count) {
+  return align_up((size_t)count * sizeof(cav::BatchMember)) + align_up(sizeof(cav::BatchCtl));
 }
 
 size_t member_bytes(const Member& m) {
@@ -370,61 +392,242 @@ int enqueue_rhs_and_walls_prep(cavity_s* h, Member& m, const double* omega) {
 }
 
 // ---------------------------------------------------------------------------
+// Batched persistent solves.
+// ---------------------------------------------------------------------------
+void destroy_graphs(cavity_s* h) {
+  for (int p = 0; p < 2; ++p) {
+    if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);
+    if (h->graph[p]) (void)hipGraphDestroy(h->graph[p]);
+    h->gexec[p] = nullptr;
+    h->graph[p] = nullptr;
+  }
+}
+
+// Descriptors of every member in the batch's tile shape, uploaded to the
+// workspace, and the co-resident grid size.
+int setup_batch(cavity_s* h) {
+  const cav::SorConfig& c = h->mixed ? h->bcfg32 : h->bcfg64;
+  if (!cav::batch_config_supported(c, h->mixed))
+    return fail(CAVITY_EINVAL, "batched kernel %dx%d s=%d nt=%d is not compiled", c.tx, c.ty, c.s,
+                c.nt);
+  h->h_mem.assign(h->count, cav::BatchMember{});
+  int tile0 = 0;
+  for (int k = 0; k < h->count; ++k) {
+    Member& m = h->m[k];
+    cav::BatchMember& b = h->h_mem[k];
+    b.psi = m.psi;
+    b.psi_b = m.psi_b;
+    b.F = m.F;
+    b.ctl = m.ctl;
+    b.part = m.part;
+    b.R32 = m.R32;
+    b.d32a = m.d32a;
+    b.d32b = m.d32b;
+    b.n = m.n;
+    b.pitch = m.pitch;
+    b.tiles_x = (m.n + c.tx - 1) / c.tx;
+    b.tiles = b.tiles_x * ((m.n + c.ty - 1) / c.ty);
+    b.tile0 = tile0;
+    tile0 += b.tiles;
+  }
+  h->total_tiles = tile0;
+  HIP_TRY(h, hipMemcpy(h->d_mem, h->h_mem.data(), h->count * sizeof(cav::BatchMember),
+                       hipMemcpyHostToDevice));
+  const int g = cav::batch_grid(c, h->mixed, h->device);
+  if (g <= 0) return fail(CAVITY_EHIP, "occupancy query for the batched kernel failed");
+  h->grid = std::min(g, h->total_tiles);
+  if (h->grid < h->count) h->grid = std::min(g, h->count);
+  if (h->grid < h->count)
+    return fail(CAVITY_EINVAL, "batch of %d cavities needs at least %d co-resident blocks",
+                h->count, h->count);
+  destroy_graphs(h);
+  return CAVITY_OK;
+}
+
+long long batch_check_sweeps(const cavity_s* h) {
+  return h->mixed ? 2LL * h->bcfg32.s * h->b_inner_pairs : 2LL * h->bcfg64.s * h->b_ppc;
+}
+
+// Enqueue one solve of every member in one persistent launch.  Like the
+// per-launch path, an FP64 solve starts with a residual check, so a warm
+// start that already meets the tolerance takes no sweep.
+int enqueue_batch_solve(cavity_s* h) {
+  for (Member& m : h->m) {
+    const double tol_hat = m.tol * 0.3 * m.h * m.h;
+    HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, m.stall_window,
+                                     batch_check_sweeps(h), h->st));
+    if (!h->mixed)
+      HIP_TRY(h, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, m.part,
+                                     h->st));
+  }
+  const long long spin = 10LL * 100000000LL;  // 10 s of the 100 MHz wall clock
+  if (!h->mixed)
+    HIP_TRY(h, cav::launch_batch64(h->bcfg64, h->d_mem, h->count, h->total_tiles, h->b_ppc,
+                                   h->d_bc, h->grid, spin, h->st));
+  else
+    HIP_TRY(h, cav::launch_batch_mixed(h->bcfg32, h->d_mem, h->count, h->total_tiles,
+                                       h->b_inner_pairs, h->d_bc, h->grid, spin, h->st));
+  for (Member& m : h->m)
+    if (m.mixed) HIP_TRY(h, cav::launch_shadow(m.psi, m.psi32, m.n, m.pitch, h->st));
+  return CAVITY_OK;
+}
+
+// Read every member's solve totals and the barrier error flag, and turn the
+// differences since the last read into this step's counts and status.
+int collect_totals(cavity_s* h, bool update_step) {
+  for (int k = 0; k < h->count; ++k)
+    HIP_TRY(h, hipMemcpyAsync(&h->host_ctl[k], h->m[k].ctl, sizeof(cav::PoissonCtl),
+                              hipMemcpyDeviceToHost, h->st));
+  HIP_TRY(h, hipMemcpyAsync(h->host_bc, h->d_bc, sizeof(cav::BatchCtl), hipMemcpyDeviceToHost,
+                            h->st));
+  HIP_TRY(h, hipStreamSynchronize(h->st));
+  if (h->last_tot.size() != (size_t)h->count) h->last_tot.assign(h->count, cav::PoissonCtl{});
+  int worst = CAVITY_OK;
+  for (int k = 0; k < h->count; ++k) {
+    const cav::PoissonCtl& c = h->host_ctl[k];
+    cav::PoissonCtl& l = h->last_tot[k];
+    if (update_step) {
+      Member& m = h->m[k];
+      const long long d = c.total_sweeps - l.total_sweeps;
+      m.sweeps_step += d;
+      m.sweeps_total += d;
+      m.last_resid = c.last * (10.0 / 3.0) / (m.h * m.h);
+      if (c.total_floor > l.total_floor) m.floor_step = 1;
+      if (c.total_nonfinite > l.total_nonfinite) {
+        h->poisoned = true;
+        worst = fail(CAVITY_ENONFINITE, "non-finite Poisson residual in cavity %d", k);
+      } else if (c.total_noconv > l.total_noconv) {
+        m.status_step = CAVITY_ENOCONV;
+        if (worst == CAVITY_OK)
+          worst = fail(CAVITY_ENOCONV, "a Poisson solve of cavity %d hit %lld sweeps", k,
+                       (long long)m.max_sweeps);
+      }
+    }
+    l = c;
+  }
+  if (h->host_bc->error) {
+    h->poisoned = true;
+    return fail(CAVITY_EHIP, "grid barrier of the batched kernel timed out (grid %d not "
+                             "co-resident?)", h->grid);
+  }
+  return worst;
+}
+
+// ---------------------------------------------------------------------------
 // One SSPRK(5,4) step of every member, stage by stage.
 // Buffers: w[0] = omega^n, w[1] = omega^(1), omega^(3), omega^(n+1);
 // w[2] = omega^(2), then the stage-5 partial sum P; w[3] = omega^(4).
 // ---------------------------------------------------------------------------
+double* stage_output(Member& m, int stage) {
+  return (stage == 2) ? m.w[2] : (stage == 4) ? m.w[3] : m.w[1];
+}
+
+int enqueue_stage(cavity_s* h, int stage) {
+  int rc;
+  for (Member& m : h->m) {
+    cav::StageArgs a{};
+    a.nu = m.nu;
+    a.h = m.h;
+    const double dt = m.dt;
+    const double* w0 = nullptr;
+    const double* win = nullptr;
+    const double* wx = nullptr;
+    double* out = nullptr;
+    const double* wp = nullptr;
+    double* pout = nullptr;
+    switch (stage) {
+      case 1:
+        win = m.w[0]; out = m.w[1]; a.a1 = 1.0; a.b = kC10 * dt;
+        break;
+      case 2:
+        w0 = m.w[0]; win = m.w[1]; out = m.w[2]; a.a0 = kA20; a.a1 = kA21; a.b = kB21 * dt;
+        break;
+      case 3:
+        w0 = m.w[0]; win = m.w[2]; out = m.w[1]; a.a0 = kA30; a.a1 = kA32; a.b = kB32 * dt;
+        break;
+      case 4:
+        w0 = m.w[0]; win = m.w[1]; out = m.w[3]; a.a0 = kA40; a.a1 = kA43; a.b = kB43 * dt;
+        wp = m.w[2]; pout = m.w[2]; a.pa = kA52; a.pb = kA53; a.pl = kB53 * dt;
+        break;
+      default:
+        win = m.w[3]; wx = m.w[2]; out = m.w[1]; a.a1 = kA54; a.ax = 1.0; a.b = kB54 * dt;
+        break;
+    }
+    HIP_TRY(h, cav::launch_stage(m.psi, m.mixed ? m.psi32 : nullptr, w0, win, wx, out, wp, pout,
+                                 m.n, m.pitch, a, h->st));
+    if ((rc = enqueue_rhs_and_walls_prep(h, m, out)) != CAVITY_OK) return rc;
+  }
+  return CAVITY_OK;
+}
+
+int enqueue_thom(cavity_s* h, int stage) {
+  for (Member& m : h->m)
+    HIP_TRY(h, cav::launch_thom(m.psi, stage_output(m, stage), m.n, m.pitch, m.h, m.u_lid,
+                                h->st));
+  return CAVITY_OK;
+}
+
+// The whole step as pure enqueues (persistent solves): what a graph captures.
+int enqueue_step_persistent(cavity_s* h) {
+  int rc;
+  for (int stage = 1; stage <= 5; ++stage) {
+    if ((rc = enqueue_stage(h, stage)) != CAVITY_OK) return rc;
+    if ((rc = enqueue_batch_solve(h)) != CAVITY_OK) return rc;
+    if ((rc = enqueue_thom(h, stage)) != CAVITY_OK) return rc;
+  }
+  return CAVITY_OK;
+}
+
+int launch_step_graph(cavity_s* h) {
+  const int parity = (h->m[0].w[0] == h->w0_base) ? 0 : 1;
+  if (!h->gexec[parity]) {
+    // The caller's stream may be the legacy null stream, which cannot be
+    // captured: record on a private stream, replay on the caller's.
+    if (!h->cap_st) HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_st, hipStreamNonBlocking));
+    HIP_TRY(h, hipStreamBeginCapture(h->cap_st, hipStreamCaptureModeThreadLocal));
+    hipStream_t user = h->st;
+    h->st = h->cap_st;
+    const int rc = enqueue_step_persistent(h);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap_st, &g);
+    h->st = user;
+    if (rc != CAVITY_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      h->poisoned = true;
+      return rc != CAVITY_OK ? rc : fail(CAVITY_EHIP, "graph capture failed: %s",
+                                          hipGetErrorString(e));
+    }
+    h->graph[parity] = g;
+    HIP_TRY(h, hipGraphInstantiate(&h->gexec[parity], g, nullptr, nullptr, 0));
+  }
+  HIP_TRY(h, hipGraphLaunch(h->gexec[parity], h->st));
+  return CAVITY_OK;
+}
+
 int step_all(cavity_s* h, bool want_diag) {
   int rc, worst = CAVITY_OK;
-  std::vector<int> all(h->count);
-  for (int k = 0; k < h->count; ++k) all[k] = k;
   for (Member& m : h->m) {
     m.sweeps_step = 0;
     m.floor_step = 0;
     m.status_step = CAVITY_OK;
     if (want_diag) HIP_TRY(h, cav::launch_copy(m.psi, m.psi_prev, m.n, m.pitch, h->st));
   }
-  for (int stage = 1; stage <= 5; ++stage) {
-    for (Member& m : h->m) {
-      cav::StageArgs a{};
-      a.nu = m.nu;
-      a.h = m.h;
-      const double dt = m.dt;
-      const double* w0 = nullptr;
-      const double* win = nullptr;
-      const double* wx = nullptr;
-      double* out = nullptr;
-      const double* wp = nullptr;
-      double* pout = nullptr;
-      switch (stage) {
-        case 1:
-          win = m.w[0]; out = m.w[1]; a.a1 = 1.0; a.b = kC10 * dt;
-          break;
-        case 2:
-          w0 = m.w[0]; win = m.w[1]; out = m.w[2]; a.a0 = kA20; a.a1 = kA21; a.b = kB21 * dt;
-          break;
-        case 3:
-          w0 = m.w[0]; win = m.w[2]; out = m.w[1]; a.a0 = kA30; a.a1 = kA32; a.b = kB32 * dt;
-          break;
-        case 4:
-          w0 = m.w[0]; win = m.w[1]; out = m.w[3]; a.a0 = kA40; a.a1 = kA43; a.b = kB43 * dt;
-          wp = m.w[2]; pout = m.w[2]; a.pa = kA52; a.pb = kA53; a.pl = kB53 * dt;
-          break;
-        default:
-          win = m.w[3]; wx = m.w[2]; out = m.w[1]; a.a1 = kA54; a.ax = 1.0; a.b = kB54 * dt;
-          break;
-      }
-      HIP_TRY(h, cav::launch_stage(m.psi, m.mixed ? m.psi32 : nullptr, w0, win, wx, out, wp, pout,
-                                   m.n, m.pitch, a, h->st));
-      if ((rc = enqueue_rhs_and_walls_prep(h, m, out)) != CAVITY_OK) return rc;
+  if (h->exec == CAVITY_EXEC_STREAM) {
+    std::vector<int> all(h->count);
+    for (int k = 0; k < h->count; ++k) all[k] = k;
+    for (int stage = 1; stage <= 5; ++stage) {
+      if ((rc = enqueue_stage(h, stage)) != CAVITY_OK) return rc;
+      rc = solve_members(h, all);
+      if (rc == CAVITY_ENONFINITE || rc == CAVITY_EHIP) return rc;
+      if (rc != CAVITY_OK) worst = rc;
+      if ((rc = enqueue_thom(h, stage)) != CAVITY_OK) return rc;
     }
-    rc = solve_members(h, all);
+  } else {
+    rc = (h->exec == CAVITY_EXEC_GRAPH) ? launch_step_graph(h) : enqueue_step_persistent(h);
+    if (rc != CAVITY_OK) return rc;
+    rc = collect_totals(h, true);
     if (rc == CAVITY_ENONFINITE || rc == CAVITY_EHIP) return rc;
     if (rc != CAVITY_OK) worst = rc;
-    for (Member& m : h->m) {
-      double* out = (stage == 2) ? m.w[2] : (stage == 4) ? m.w[3] : m.w[1];
-      HIP_TRY(h, cav::launch_thom(m.psi, out, m.n, m.pitch, m.h, m.u_lid, h->st));
-    }
   }
   for (Member& m : h->m) {
     std::swap(m.w[0], m.w[1]);  // omega^(n+1) becomes the state; omega^n kept in w[1]
@@ -449,7 +652,7 @@ const char* cavity_last_error(void) { return g_err.c_str(); }
 int cavity_workspace_bytes(const cavity_params* p, int32_t count, size_t* bytes) {
   if (!p || !bytes) return fail(CAVITY_EINVAL, "null argument");
   if (count < 1) return fail(CAVITY_EINVAL, "count must be >= 1");
-  size_t total = 0;
+  size_t total = handle_bytes(count);
   for (int k = 0; k < count; ++k) {
     Member m;
     const int rc = derive(p[k], m);
@@ -482,26 +685,39 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
     }
     need += member_bytes(h->m[k]);
   }
+  need += handle_bytes(count);
   if (ws_bytes < need) {
     delete h;
     return fail(CAVITY_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
   }
+  h->mixed = h->m[0].mixed;
+  bool uniform = true;
+  for (const Member& m : h->m) uniform = uniform && (m.mixed == h->mixed);
   if (hipGetDevice(&h->device) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&h->host_ctl), count * sizeof(cav::PoissonCtl)) !=
           hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&h->host_diag), count * 4 * sizeof(double)) !=
-          hipSuccess) {
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&h->host_bc), sizeof(cav::BatchCtl)) != hipSuccess) {
     cavity_destroy(h);
     return fail(CAVITY_EHIP, "pinned host allocation failed");
   }
   char* cur = static_cast<char*>(d_ws);
   for (Member& m : h->m) carve(m, cur);
+  h->d_mem = reinterpret_cast<cav::BatchMember*>(cur);
+  cur += align_up((size_t)count * sizeof(cav::BatchMember));
+  h->d_bc = reinterpret_cast<cav::BatchCtl*>(cur);
+  h->w0_base = h->m[0].w[0];
 
   auto bail = [&](int rc) {
     cavity_destroy(h);
     return rc;
   };
+  if (cav::launch_zero(h->d_bc, sizeof(cav::BatchCtl), h->st) != hipSuccess)
+    return bail(fail(CAVITY_EHIP, "zero fill failed"));
   for (Member& m : h->m) {
+    if (cav::launch_zero(m.ctl, sizeof(cav::PoissonCtl), h->st) != hipSuccess)
+      return bail(fail(CAVITY_EHIP, "zero fill failed"));
     for (int k = 0; k < 4; ++k)
       if (cav::launch_fill(m.w[k], m.n, m.pitch, 0.0, h->st) != hipSuccess)
         return bail(fail(CAVITY_EHIP, "fill failed"));
@@ -547,6 +763,24 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
   for (Member& m : h->m) {
     m.sweeps_total = 0;
     m.sweeps_step = 0;
+  }
+  // Batch defaults: the FP64 tile shape that measured fastest; residual
+  // checks every 32 sweeps; FP32 rounds as long as the largest member's.
+  {
+    int inner = 0;
+    for (const Member& m : h->m) inner = std::max(inner, m.inner_sweeps);
+    const int small = h->m[0].n <= 320 && count == 1;
+    h->bcfg64 = small ? cav::SorConfig{32, 32, 1, 256, 0} : cav::SorConfig{64, 64, 4, 1024, 0};
+    h->bcfg32 = small ? cav::SorConfig{32, 32, 1, 256, 0} : cav::SorConfig{64, 64, 4, 1024, 0};
+    h->b_ppc = std::max(1, 32 / (2 * h->bcfg64.s));
+    h->b_inner_pairs = std::max(1, (inner + 2 * h->bcfg32.s - 1) / (2 * h->bcfg32.s));
+  }
+  const int rc2 = collect_totals(h, false);
+  if (rc2 != CAVITY_OK) return bail(rc2);
+  if (count > 1 && uniform) {
+    const int rc3 = setup_batch(h);
+    if (rc3 != CAVITY_OK) return bail(rc3);
+    h->exec = CAVITY_EXEC_GRAPH;
   }
   *out = h;
   return rc;
@@ -696,6 +930,22 @@ int cavity_relax(cavity_t h, int32_t idx, int32_t sweeps, int32_t arith, double*
 
 int cavity_get_tuning(cavity_t h, int32_t idx, cavity_tuning* t) {
   if (!h || !t) return fail(CAVITY_EINVAL, "null argument");
+  if (idx == -1) {
+    std::memset(t, 0, sizeof *t);
+    t->tile_x = h->bcfg64.tx;
+    t->tile_y = h->bcfg64.ty;
+    t->sweeps_per_launch = h->bcfg64.s;
+    t->threads = h->bcfg64.nt;
+    t->tile_x32 = h->bcfg32.tx;
+    t->tile_y32 = h->bcfg32.ty;
+    t->sweeps_per_launch32 = h->bcfg32.s;
+    t->threads32 = h->bcfg32.nt;
+    t->check_every = (int32_t)(2LL * h->bcfg64.s * h->b_ppc);
+    t->inner_sweeps = 2 * h->bcfg32.s * h->b_inner_pairs;
+    t->xcd_bands = 0;
+    t->sor_omega = 0.0;
+    return CAVITY_OK;
+  }
   if (idx < 0 || idx >= h->count) return fail(CAVITY_EINVAL, "idx %d out of range", idx);
   const Member& m = h->m[idx];
   std::memset(t, 0, sizeof *t);
@@ -716,7 +966,26 @@ int cavity_get_tuning(cavity_t h, int32_t idx, cavity_tuning* t) {
 
 int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t) {
   if (!h || !t) return fail(CAVITY_EINVAL, "null argument");
+  if (idx == -1) {
+    const cav::SorConfig c64{t->tile_x, t->tile_y, t->sweeps_per_launch, t->threads, 0};
+    const cav::SorConfig c32{t->tile_x32, t->tile_y32, t->sweeps_per_launch32, t->threads32, 0};
+    if (!cav::batch_config_supported(c64, false) || !cav::batch_config_supported(c32, true))
+      return fail(CAVITY_EINVAL, "batched kernel configuration is not compiled");
+    if (t->check_every < 1 || t->inner_sweeps < 1)
+      return fail(CAVITY_EINVAL, "check_every and inner_sweeps must be >= 1");
+    h->bcfg64 = c64;
+    h->bcfg32 = c32;
+    h->b_ppc = std::max(1, (t->check_every + 2 * c64.s - 1) / (2 * c64.s));
+    h->b_inner_pairs = std::max(1, (t->inner_sweeps + 2 * c32.s - 1) / (2 * c32.s));
+    if (h->exec != CAVITY_EXEC_STREAM) {
+      HIP_TRY(h, hipSetDevice(h->device));
+      return setup_batch(h);
+    }
+    destroy_graphs(h);
+    return CAVITY_OK;
+  }
   if (idx < 0 || idx >= h->count) return fail(CAVITY_EINVAL, "idx %d out of range", idx);
+  destroy_graphs(h);
   const cav::SorConfig c64{t->tile_x, t->tile_y, t->sweeps_per_launch, t->threads, t->xcd_bands};
   const cav::SorConfig c32{t->tile_x32, t->tile_y32, t->sweeps_per_launch32, t->threads32,
                            t->xcd_bands};
@@ -739,8 +1008,37 @@ int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t) {
   return CAVITY_OK;
 }
 
+int cavity_get_exec(cavity_t h, int32_t* mode) {
+  if (!h || !mode) return fail(CAVITY_EINVAL, "null argument");
+  *mode = h->exec;
+  return CAVITY_OK;
+}
+
+int cavity_set_exec(cavity_t h, int32_t mode) {
+  if (!h) return fail(CAVITY_EINVAL, "null handle");
+  if (h->poisoned) return fail(CAVITY_ESTATE, "handle poisoned by an earlier failure");
+  if (mode != CAVITY_EXEC_STREAM && mode != CAVITY_EXEC_PERSISTENT && mode != CAVITY_EXEC_GRAPH)
+    return fail(CAVITY_EINVAL, "unknown execution mode %d", mode);
+  HIP_TRY(h, hipSetDevice(h->device));
+  if (mode != CAVITY_EXEC_STREAM) {
+    for (const Member& m : h->m)
+      if (m.mixed != h->mixed)
+        return fail(CAVITY_EINVAL, "batched execution needs one precision for all cavities");
+    int rc = setup_batch(h);
+    if (rc != CAVITY_OK) return rc;
+    rc = collect_totals(h, false);
+    if (rc != CAVITY_OK) return rc;
+  }
+  destroy_graphs(h);
+  h->exec = mode;
+  return CAVITY_OK;
+}
+
 int cavity_destroy(cavity_t h) {
   if (!h) return CAVITY_OK;
+  destroy_graphs(h);
+  if (h->cap_st) (void)hipStreamDestroy(h->cap_st);
+  if (h->host_bc) (void)hipHostFree(h->host_bc);
   if (h->host_ctl) (void)hipHostFree(h->host_ctl);
   if (h->host_diag) (void)hipHostFree(h->host_diag);
   delete h;

@@ -61,7 +61,7 @@ def test_workspace_bytes_scales_with_grid(binding):
     mixed = binding.cavity_workspace_bytes([P(n=1024, precision=binding.CAVITY_MIXED).to_c()])
     assert mixed >= big + 3 * 1024 * 1024 * 4
     two = binding.cavity_workspace_bytes([P(n=64).to_c(), P(n=1024).to_c()])
-    assert two == small + big
+    assert abs(two - (small + big)) <= 1024   # one shared handle area instead of two
 
 
 @pytest.mark.parametrize("kw,msg", [

@@ -1,0 +1,86 @@
+"""Batched Reynolds sweeps: one persistent launch per stage solves every cavity
+(grid barriers between sweep rounds, per-cavity stopping decisions on the
+device), optionally with the whole step captured in a hipGraph.
+
+A persistent round is the same arithmetic as one launch of the per-cavity
+path, so with the same sweeps per launch, check spacing and relaxation the
+batched results are bitwise those of each cavity run on its own.
+"""
+import numpy as np
+import pytest
+
+from oracle.cavity_oracle import CavityOracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_0809_3098_amd.cavity as cav
+    return cav
+
+
+def _solo(cm, n, re, precision, s, check_every, inner):
+    c = cm.Cavity(cm.Params(n=n, re=re, precision=precision))
+    t = c.tuning()
+    c.set_tuning(tile_x=64, tile_y=64, sweeps_per_launch=s, threads=1024,
+                 tile_x32=64, tile_y32=64, sweeps_per_launch32=s, threads32=1024,
+                 check_every=check_every, inner_sweeps=inner, xcd_bands=0,
+                 sor_omega=t["sor_omega"])
+    return c
+
+
+@pytest.mark.parametrize("mode", ["persistent", "graph"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_bitwise_equals_solo_runs(cm, mode, precision):
+    """Every step (every graph replay, with host work in between) is compared."""
+    members = [(5000.0, 130), (10000.0, 200), (15000.0, 257)]
+    steps, s, check_every, inner = 4, 2, 8, 256
+    print(f"[batch {mode} precision={precision}] {members}", flush=True)
+    c = cm.Cavity([cm.Params(n=n, re=re, precision=precision) for re, n in members])
+    c.set_exec(cm.CAVITY_EXEC_PERSISTENT if mode == "persistent" else cm.CAVITY_EXEC_GRAPH)
+    c.set_tuning(-1, tile_x=64, tile_y=64, sweeps_per_launch=s, threads=1024,
+                 tile_x32=64, tile_y32=64, sweeps_per_launch32=s, threads32=1024,
+                 check_every=check_every, inner_sweeps=inner)
+    solos = [_solo(cm, n, re, precision, s, check_every, inner) for re, n in members]
+    for step in range(steps):
+        stats = c.step(1)
+        for k, solo in enumerate(solos):
+            st = solo.step(1)[0]
+            p, w, _, _ = solo.fields()
+            gp, gw, _, _ = c.fields(k)
+            assert np.array_equal(gp, p), (step, k)
+            assert np.array_equal(gw, w), (step, k)
+            assert stats[k]["sweeps_last_step"] == st["sweeps_last_step"], (step, k)
+            assert stats[k]["status"] == 0
+    c.close()
+    for solo in solos:
+        solo.close()
+
+
+def test_reynolds_sweep_six_cavities_graph(cm):
+    """The six-cavity Reynolds sweep (256^2 ... 1024^2) in graph mode."""
+    members = [(5000.0, 256), (10000.0, 512), (15000.0, 768), (20000.0, 1024),
+               (25000.0, 1024), (30000.0, 1024)]
+    steps = 3
+    print("[re sweep] six cavities", flush=True)
+    c = cm.Cavity([cm.Params(n=n, re=re) for re, n in members])
+    assert c.exec_mode() == cm.CAVITY_EXEC_GRAPH
+    stats = c.step(steps)
+    fields = [c.fields(k) for k in range(len(members))]
+    c.close()
+    for k, (re, n) in enumerate(members):
+        psi, omega = fields[k][0], fields[k][1]
+        assert stats[k]["status"] == 0 and stats[k]["step"] == steps
+        assert np.all(psi[0, :] == 0) and np.all(psi[-1, :] == 0)
+        assert np.all(psi[:, 0] == 0) and np.all(psi[:, -1] == 0)
+        assert np.all(np.isfinite(omega))
+    # the smallest member against the oracle
+    ref = CavityOracle(256, 5000.0, workers=-1)
+    ref.step(steps)
+    ep = np.max(np.abs(fields[0][0] - ref.psi)) / np.max(np.abs(ref.psi))
+    ew = np.max(np.abs(fields[0][1] - ref.omega)) / np.max(np.abs(ref.omega))
+    print(f"  256^2 member: psi_rel={ep:.3e} omega_rel={ew:.3e}")
+    assert ep <= 1e-11 and ew <= 1e-11

@@ -33,8 +33,8 @@ def _inv_norm(n):
 
 
 # (n, sweeps): n <= 320 uses 32x32 tiles with 1 sweep per launch (pairs of 2),
-# larger n 64x64 tiles with 2 sweeps per launch (pairs of 4).
-@pytest.mark.parametrize("n,sweeps", [(5, 2), (33, 2), (64, 6), (97, 4), (330, 4), (400, 8),
+# larger n 64x64 tiles with 4 sweeps per launch (pairs of 8).
+@pytest.mark.parametrize("n,sweeps", [(5, 2), (33, 2), (64, 6), (97, 4), (330, 8), (400, 16),
                                       (1024, 8)])
 def test_fixed_sweeps_match_oracle_four_colour_sweeps(cav_mod, n, sweeps):
     print(f"[fixed sweeps] n={n} sweeps={sweeps}", flush=True)

@@ -114,11 +114,13 @@ def test_resume_is_bitwise(cm):
     assert np.array_equal(p, p20) and np.array_equal(w, w20)
 
 
-def test_batch_equals_sequential(cm):
+def test_batch_streams_equal_sequential(cm):
+    """count > 1 in stream mode: interleaved per-cavity solves, bitwise."""
     members = [(1000.0, 40), (3000.0, 64), (2000.0, 97)]
     steps = 6
-    print(f"[batch] {members}", flush=True)
+    print(f"[batch stream] {members}", flush=True)
     c = cm.Cavity([cm.Params(n=n, re=re) for re, n in members])
+    c.set_exec(cm.CAVITY_EXEC_STREAM)
     stats = c.step(steps)
     got = [c.fields(k) for k in range(len(members))]
     c.close()
