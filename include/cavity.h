@@ -204,9 +204,22 @@ typedef struct cavity_tuning {
                                     up to whole launch pairs)                     */
   int32_t inner_sweeps;          /* mixed: FP32 sweeps per refinement round        */
   int32_t xcd_bands;             /* 1: each XCD relaxes a contiguous band of tiles */
-  int32_t reserved;
+  int32_t solver;                /* enum cavity_solver                              */
   double sor_omega;              /* relaxation parameter in (0, 2)                 */
 } cavity_tuning;
+
+/*
+ * Poisson solver of a cavity.  Both converge the same compact equation
+ * (eq. SequationFinal's fixed point) to poisson_tol.
+ *   CAVITY_SOLVER_SOR  four-colour SOR, the paper's relaxation (default)
+ *   CAVITY_SOLVER_MG   geometric multigrid V(2,2)-cycles: four-colour
+ *                      Gauss-Seidel smoothing with the same sweep kernel,
+ *                      the compact operator rediscretised on coarser grids
+ *                      (m intervals -> ceil(m/2); non-nested levels use
+ *                      bilinear transfers in physical coordinates); FP64
+ *                      cavities in CAVITY_EXEC_STREAM only
+ */
+enum cavity_solver { CAVITY_SOLVER_SOR = 0, CAVITY_SOLVER_MG = 1 };
 
 /*
  * Read / replace the launch configuration of cavity idx (host only).  idx = -1
@@ -236,6 +249,22 @@ int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t);
 enum cavity_exec { CAVITY_EXEC_STREAM = 0, CAVITY_EXEC_PERSISTENT = 1, CAVITY_EXEC_GRAPH = 2 };
 int cavity_set_exec(cavity_t h, int32_t mode);
 int cavity_get_exec(cavity_t h, int32_t* mode);
+
+/*
+ * Autotuner.  For cavity idx: times every compiled sweep kernel (tile shape,
+ * sweeps per launch, threads, XCD-banded tile order) with back-to-back
+ * launches and keeps the fastest per FP64 / FP32 smoother; then chooses the
+ * sweep schedule (FP64: residual-check spacing; mixed: FP32 sweeps per
+ * refinement round) by timing complete Poisson solves of the cavity's current
+ * vorticity.  For idx = -1: times the batched persistent kernel per tile shape.
+ * Measurements use scratch buffers; the simulation state is not modified
+ * (results may differ in the last bits afterwards, since the schedule does).
+ * cache_path (nullable): a JSON-lines file; an entry for the same key (device
+ * architecture, n, precision, batch members) is applied without measuring,
+ * and a new result is appended.  The applied tuning is returned in *chosen
+ * (nullable).  Synchronises the stream; takes a few seconds.
+ */
+int cavity_autotune(cavity_t h, int32_t idx, const char* cache_path, cavity_tuning* chosen);
 
 /* Release the handle (host memory only; the workspace stays the caller's). */
 int cavity_destroy(cavity_t h);

@@ -36,6 +36,8 @@ CAVITY_MIXED = 1
 CAVITY_EXEC_STREAM = 0
 CAVITY_EXEC_PERSISTENT = 1
 CAVITY_EXEC_GRAPH = 2
+CAVITY_SOLVER_SOR = 0
+CAVITY_SOLVER_MG = 1
 
 _STATUS_NAMES = {0: "CAVITY_OK", -1: "CAVITY_EINVAL", -2: "CAVITY_ENOMEM", -3: "CAVITY_EHIP",
                  -4: "CAVITY_ENOCONV", -5: "CAVITY_ENONFINITE", -6: "CAVITY_ESTATE"}
@@ -89,12 +91,12 @@ class cavity_tuning(ctypes.Structure):
         ("tile_x32", ctypes.c_int32), ("tile_y32", ctypes.c_int32),
         ("sweeps_per_launch32", ctypes.c_int32), ("threads32", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("inner_sweeps", ctypes.c_int32),
-        ("xcd_bands", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("xcd_bands", ctypes.c_int32), ("solver", ctypes.c_int32),
         ("sor_omega", ctypes.c_double),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _P = ctypes.POINTER
@@ -110,18 +112,21 @@ _lib.cavity_relax.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, c
                               ctypes.c_void_p, _P(ctypes.c_int64)]
 _lib.cavity_get_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(cavity_tuning)]
 _lib.cavity_set_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(cavity_tuning)]
+_lib.cavity_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p,
+                                 _P(cavity_tuning)]
 _lib.cavity_set_exec.argtypes = [ctypes.c_void_p, ctypes.c_int32]
 _lib.cavity_get_exec.argtypes = [ctypes.c_void_p, _P(ctypes.c_int32)]
 _lib.cavity_destroy.argtypes = [ctypes.c_void_p]
 _lib.cavity_last_error.restype = ctypes.c_char_p
 for _f in ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_poisson",
            "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
-           "cavity_set_exec", "cavity_get_exec", "cavity_destroy"):
+           "cavity_set_exec", "cavity_get_exec", "cavity_autotune", "cavity_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_poisson",
             "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
-            "cavity_set_exec", "cavity_get_exec", "cavity_destroy", "cavity_last_error")
+            "cavity_set_exec", "cavity_get_exec", "cavity_autotune", "cavity_destroy",
+            "cavity_last_error")
 
 
 def cavity_last_error() -> str:
@@ -232,6 +237,13 @@ def cavity_set_tuning(h: int, idx: int, **kw) -> dict:
     return cavity_get_tuning(h, idx)
 
 
+def cavity_autotune(h: int, idx: int, cache_path: Optional[str] = None) -> dict:
+    t = cavity_tuning()
+    path = cache_path.encode() if cache_path else None
+    _check(_lib.cavity_autotune(ctypes.c_void_p(h), idx, path, ctypes.byref(t)))
+    return t.as_dict()
+
+
 def cavity_set_exec(h: int, mode: int) -> None:
     _check(_lib.cavity_set_exec(ctypes.c_void_p(h), mode))
 
@@ -331,6 +343,9 @@ class Cavity:
 
     def set_tuning(self, idx: int = 0, **kw) -> dict:
         return cavity_set_tuning(self.handle, idx, **kw)
+
+    def autotune(self, idx: int = 0, cache_path: Optional[str] = None) -> dict:
+        return cavity_autotune(self.handle, idx, cache_path)
 
     def set_exec(self, mode: int) -> None:
         cavity_set_exec(self.handle, mode)

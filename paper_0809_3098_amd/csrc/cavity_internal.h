@@ -65,13 +65,18 @@ struct BatchMember {
   int pad;
 };
 
-// Grid barrier and error flag of the persistent kernels.
+// Grid barrier state and error flag of the persistent kernels.  Barrier
+// generations only grow, across launches too: `epoch` is the generation the
+// last launch ended with, `go` the last generation released by block 0.
+// Arrival flags live in a separate array, one 128-byte line per block.
 struct alignas(128) BatchCtl {
-  unsigned int bar_count;
-  unsigned int bar_gen;
+  unsigned int epoch;
+  unsigned int go;
   int error;           // 1: a barrier wait timed out (blocks not co-resident)
   int pad;
 };
+constexpr int kMaxBatchGrid = 4096;        // blocks of a persistent launch
+constexpr int kFlagStride = 32;            // words between two arrival flags
 
 // Tile configuration of the temporally blocked four-colour sweep.
 struct SorConfig {
@@ -133,21 +138,38 @@ hipError_t launch_sor32(const SorConfig& cfg, const float* d_in, float* d_out, c
 // 100 MHz wall clock and set BatchCtl::error when exceeded.
 // FP64: pairs_per_check launch-pairs of cfg.s sweeps between checks.
 hipError_t launch_batch64(const SorConfig& cfg, const BatchMember* mem, int count,
-                          int total_tiles, int pairs_per_check, BatchCtl* bc, int grid,
-                          long long spin_ticks, hipStream_t st);
+                          int total_tiles, int pairs_per_check, BatchCtl* bc,
+                          unsigned int* flags, int grid, long long spin_ticks, hipStream_t st);
 // Mixed: rounds of FP64 residual, inner_pairs FP32 launch-pairs (the last
 // pair Gauss-Seidel) and FP64 refinement.
 hipError_t launch_batch_mixed(const SorConfig& cfg32, const BatchMember* mem, int count,
-                              int total_tiles, int inner_pairs, BatchCtl* bc, int grid,
-                              long long spin_ticks, hipStream_t st);
+                              int total_tiles, int inner_pairs, BatchCtl* bc,
+                              unsigned int* flags, int grid, long long spin_ticks,
+                              hipStream_t st);
 // Largest co-resident grid for the batched kernel of this configuration.
 int batch_grid(const SorConfig& cfg, bool mixed, int device);
 bool batch_config_supported(const SorConfig& cfg, bool mixed);
 
 // Mixed precision: FP64 residual r = g(psi) - psi into R32 (as float), zero
 // d32, reduce max |r| and take the solve decision.
+// sweeps_done: sweeps since the previous check, added to the solve's count.
 hipError_t launch_resid64(const double* psi, const double* F, float* R32, float* d32, int n,
-                          int pitch, PoissonCtl* ctl, double* part, hipStream_t st);
+                          int pitch, PoissonCtl* ctl, double* part, hipStream_t st,
+                          long long sweeps_done = 0);
+
+// Multigrid: residual in vorticity units, restriction to the next coarser
+// level (also zeroing its iterate), prolongation-and-correct, and a sweep
+// launch with an explicit relaxation parameter (no residual check).
+hipError_t launch_mg_residual(const double* psi, const double* F, double* r, int n, int pitch,
+                              double h, const PoissonCtl* ctl, hipStream_t st);
+hipError_t launch_mg_restrict(const double* r, int nf, int pitchf, double* Fc, double* Ec,
+                              double* Ecb, int nc, int pitchc, const PoissonCtl* ctl,
+                              hipStream_t st);
+hipError_t launch_mg_prolong(const double* Ec, int nc, int pitchc, double* psi, int nf,
+                             int pitchf, const PoissonCtl* ctl, hipStream_t st);
+hipError_t launch_sor64_relax(const SorConfig& cfg, const double* psi_in, double* psi_out,
+                              const double* F, int n, int pitch, PoissonCtl* ctl, double relax,
+                              hipStream_t st);
 // psi64 += d32 on interior nodes and count the inner sweeps (skipped once
 // the solve has stopped).
 hipError_t launch_refine(double* psi, const float* d32, int n, int pitch, PoissonCtl* ctl,

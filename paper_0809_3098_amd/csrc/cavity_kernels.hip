@@ -352,39 +352,73 @@ __device__ inline int load_state(const PoissonCtl* c) {
   return __hip_atomic_load(&c->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sense-reversing grid barrier.  Returns false (and sets bc->error) if a wait
-// exceeds spin_ticks of the wall clock, so a grid that is not co-resident
-// ends with an error instead of hanging.
-__device__ bool grid_sync(BatchCtl* bc, unsigned int nb, long long spin_ticks) {
+// Grid barrier.  Every block stores the new generation in its own arrival
+// flag (one 128-byte line each, so arrivals never contend); the threads of
+// block 0 wait for all flags in parallel and then release the generation in
+// `go`, which the other blocks wait for.  Returns false (and sets bc->error)
+// if a wait exceeds spin_ticks of the 100 MHz wall clock, so a grid that is
+// not co-resident ends with an error instead of hanging.
+__device__ bool grid_sync(BatchCtl* bc, unsigned int* flags, unsigned int nb, unsigned int& gen,
+                          long long spin_ticks) {
   __shared__ int s_ok;
   __syncthreads();
+  gen += 1u;
   if (threadIdx.x == 0) {
-    int ok = 1;
     __threadfence();
-    const unsigned int g = __hip_atomic_load(&bc->bar_gen, __ATOMIC_ACQUIRE,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned int a = __hip_atomic_fetch_add(&bc->bar_count, 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-    if (a == nb - 1) {
-      __hip_atomic_store(&bc->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bc->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      const long long t0 = wall_clock64();
-      while (__hip_atomic_load(&bc->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(2);
+    __hip_atomic_store(&flags[blockIdx.x * kFlagStride], gen, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  int ok = 1;
+  if (blockIdx.x == 0) {
+    const long long t0 = wall_clock64();
+    for (unsigned int b = threadIdx.x; b < nb && ok; b += blockDim.x) {
+      while (__hip_atomic_load(&flags[b * kFlagStride], __ATOMIC_ACQUIRE,
+                               __HIP_MEMORY_SCOPE_AGENT) != gen) {
+        __builtin_amdgcn_s_sleep(1);
         if (__hip_atomic_load(&bc->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
             wall_clock64() - t0 > spin_ticks) {
-          __hip_atomic_store(&bc->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
           break;
         }
       }
     }
+    ok = __syncthreads_and(ok);
+    if (threadIdx.x == 0) {
+      if (ok) {
+        __threadfence();
+        __hip_atomic_store(&bc->go, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        __hip_atomic_store(&bc->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  } else if (threadIdx.x == 0) {
+    const long long t0 = wall_clock64();
+    while (__hip_atomic_load(&bc->go, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != gen) {
+      __builtin_amdgcn_s_sleep(1);
+      if (__hip_atomic_load(&bc->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          wall_clock64() - t0 > spin_ticks) {
+        __hip_atomic_store(&bc->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
     __threadfence();
     s_ok = ok;
   }
   __syncthreads();
   return s_ok != 0;
+}
+
+// The generation every block starts a launch with, and the record of the
+// one it ended with (block 0, after the last barrier every block passed).
+__device__ inline unsigned int batch_epoch(const BatchCtl* bc) {
+  return __hip_atomic_load(&bc->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void batch_end(BatchCtl* bc, unsigned int gen) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&bc->epoch, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline int member_of(const BatchMember* mem, int count, int t) {
@@ -426,11 +460,14 @@ __device__ void batch_decide(const BatchMember* mem, int count, long long sweeps
 template <int TX, int TY, int S, int NT>
 __global__ __launch_bounds__(NT) void k_batch64(const BatchMember* __restrict__ mem, int count,
                                                 int total_tiles, int pairs_per_check,
-                                                BatchCtl* __restrict__ bc, long long spin_ticks) {
+                                                BatchCtl* __restrict__ bc,
+                                                unsigned int* __restrict__ flags,
+                                                long long spin_ticks) {
   using G = SorGeom<double, TX, TY, S>;
   __shared__ double sp[4 * G::PLANE];
   __shared__ double sf[4 * G::PLANE];
   const unsigned int nb = gridDim.x;
+  unsigned int gen = batch_epoch(bc);
   while (any_running(mem, count)) {
     for (int r = 0; r < 2 * pairs_per_check; ++r) {
       const bool fwd = (r & 1) == 0;
@@ -456,22 +493,25 @@ __global__ __launch_bounds__(NT) void k_batch64(const BatchMember* __restrict__ 
         }
         __syncthreads();
       }
-      if (!grid_sync(bc, nb, spin_ticks)) return;
+      if (!grid_sync(bc, flags, nb, gen, spin_ticks)) return;
     }
     batch_decide<NT>(mem, count, -1);
-    if (!grid_sync(bc, nb, spin_ticks)) return;
+    if (!grid_sync(bc, flags, nb, gen, spin_ticks)) return;
   }
+  batch_end(bc, gen);
 }
 
 template <int TX, int TY, int S, int NT>
 __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restrict__ mem,
                                                     int count, int total_tiles, int inner_pairs,
                                                     BatchCtl* __restrict__ bc,
+                                                    unsigned int* __restrict__ flags,
                                                     long long spin_ticks) {
   using G = SorGeom<float, TX, TY, S>;
   __shared__ float sp[4 * G::PLANE];
   __shared__ float sf[4 * G::PLANE];
   const unsigned int nb = gridDim.x;
+  unsigned int gen = batch_epoch(bc);
   for (;;) {
     // FP64 residual of psi on every tile; the correction starts from zero.
     for (int t = blockIdx.x; t < total_tiles; t += nb) {
@@ -501,10 +541,13 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
       }
       __syncthreads();
     }
-    if (!grid_sync(bc, nb, spin_ticks)) return;
+    if (!grid_sync(bc, flags, nb, gen, spin_ticks)) return;
     batch_decide<NT>(mem, count, 0);
-    if (!grid_sync(bc, nb, spin_ticks)) return;
-    if (!any_running(mem, count)) return;
+    if (!grid_sync(bc, flags, nb, gen, spin_ticks)) return;
+    if (!any_running(mem, count)) {
+      batch_end(bc, gen);
+      return;
+    }
     // FP32 correction sweeps; the last pair relaxes with 1.
     for (int r = 0; r < 2 * inner_pairs; ++r) {
       const bool fwd = (r & 1) == 0;
@@ -518,7 +561,7 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
                                               sp, sf, rm, pm);
         __syncthreads();
       }
-      if (!grid_sync(bc, nb, spin_ticks)) return;
+      if (!grid_sync(bc, flags, nb, gen, spin_ticks)) return;
     }
     // FP64 refinement psi += d, and the sweep count.
     for (int t = blockIdx.x; t < total_tiles; t += nb) {
@@ -538,8 +581,103 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
         m.ctl->total_sweeps += done;
       }
     }
-    if (!grid_sync(bc, nb, spin_ticks)) return;
+    if (!grid_sync(bc, flags, nb, gen, spin_ticks)) return;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Geometric multigrid for the compact stream equation (coarse levels are the
+// same compact operator rediscretised on a coarser grid).  A level with m
+// intervals (h = 1/m) coarsens to ceil(m/2) intervals; for odd m the grids
+// are not nested, so transfers work in physical coordinates: prolongation is
+// bilinear interpolation, restriction its transpose scaled by (h_f/h_c)^2.
+// With x_i = i/m_f and X_I = I/m_c the hat weight of coarse node I at fine
+// node i is 1 - |i m_c - I m_f| / m_f, evaluated exactly in integers; on
+// nested levels these are the usual bilinear and full-weighting stencils.
+// Every kernel returns at once when the solve has stopped.
+// ---------------------------------------------------------------------------
+// r = (g - psi) / (0.3 h^2): the residual of the compact equation in
+// vorticity units (zero on walls).
+__global__ __launch_bounds__(kBlock) void k_mg_residual(const double* __restrict__ psi,
+                                                        const double* __restrict__ F,
+                                                        double* __restrict__ r, int n, int pitch,
+                                                        double inv03h2,
+                                                        const PoissonCtl* __restrict__ ctl) {
+  if (ctl->state != SOLVE_RUN) return;
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= n || j >= n) return;
+  const size_t p = (size_t)j * pitch + i;
+  if (i == 0 || j == 0 || i == n - 1 || j == n - 1) {
+    r[p] = 0.0;
+    return;
+  }
+  const double s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pitch] + psi[p - pitch]);
+  const double sd = (psi[p + pitch + 1] + psi[p + pitch - 1]) +
+                    (psi[p - pitch + 1] + psi[p - pitch - 1]);
+  const double g = fma(0.2, s4, fma(0.05, sd, F[p]));
+  r[p] = (g - psi[p]) * inv03h2;
+}
+
+// Coarse right-hand side F_c = 0.3 h_c^2 R r and a zero coarse iterate (both
+// ping-pong buffers, walls included).
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(const double* __restrict__ r, int nf,
+                                                        int pitchf, double* __restrict__ Fc,
+                                                        double* __restrict__ Ec,
+                                                        double* __restrict__ Ecb, int nc,
+                                                        int pitchc, double scale,
+                                                        const PoissonCtl* __restrict__ ctl) {
+  if (ctl->state != SOLVE_RUN) return;
+  const int I = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int J = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (I >= nc || J >= nc) return;
+  const size_t pc = (size_t)J * pitchc + I;
+  Ec[pc] = 0.0;
+  Ecb[pc] = 0.0;
+  if (I == 0 || J == 0 || I == nc - 1 || J == nc - 1) {
+    Fc[pc] = 0.0;
+    return;
+  }
+  const long long mf = nf - 1, mc = nc - 1;
+  const int i0 = max(1, (int)(((I - 1) * mf) / mc) + 1);
+  const int i1 = min(nf - 2, (int)(((I + 1) * mf + mc - 1) / mc) - 1);
+  const int j0 = max(1, (int)(((J - 1) * mf) / mc) + 1);
+  const int j1 = min(nf - 2, (int)(((J + 1) * mf + mc - 1) / mc) - 1);
+  const double invmf = 1.0 / (double)mf;
+  double sum = 0.0;
+  for (int j = j0; j <= j1; ++j) {
+    const long long dj = (long long)j * mc - (long long)J * mf;
+    const double wy = (double)(mf - (dj < 0 ? -dj : dj)) * invmf;
+    if (wy <= 0.0) continue;
+    double row = 0.0;
+    for (int i = i0; i <= i1; ++i) {
+      const long long di = (long long)i * mc - (long long)I * mf;
+      const double wx = (double)(mf - (di < 0 ? -di : di)) * invmf;
+      if (wx > 0.0) row = fma(wx, r[(size_t)j * pitchf + i], row);
+    }
+    sum = fma(wy, row, sum);
+  }
+  Fc[pc] = scale * sum;
+}
+
+// psi_f += P E_c (bilinear interpolation of the coarse correction).
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(const double* __restrict__ Ec, int nc,
+                                                       int pitchc, double* __restrict__ psi,
+                                                       int nf, int pitchf,
+                                                       const PoissonCtl* __restrict__ ctl) {
+  if (ctl->state != SOLVE_RUN) return;
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i < 1 || j < 1 || i > nf - 2 || j > nf - 2) return;
+  const long long mf = nf - 1, mc = nc - 1;
+  const int I = (int)(((long long)i * mc) / mf);
+  const int J = (int)(((long long)j * mc) / mf);
+  const double ti = (double)((long long)i * mc - (long long)I * mf) / (double)mf;
+  const double tj = (double)((long long)j * mc - (long long)J * mf) / (double)mf;
+  const size_t c = (size_t)J * pitchc + I;
+  const double lo = fma(ti, Ec[c + 1] - Ec[c], Ec[c]);
+  const double hi = fma(ti, Ec[c + pitchc + 1] - Ec[c + pitchc], Ec[c + pitchc]);
+  psi[(size_t)j * pitchf + i] += fma(tj, hi - lo, lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -677,7 +815,8 @@ __global__ __launch_bounds__(kBlock) void k_resid64(const double* __restrict__ p
                                                     float* __restrict__ R32,
                                                     float* __restrict__ d32, int n, int pitch,
                                                     PoissonCtl* __restrict__ ctl,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part,
+                                                    long long sweeps_done) {
   if (ctl->state != SOLVE_RUN) return;
   double rmax = 0.0, pmax = 0.0;
   const int m = n - 2;
@@ -699,7 +838,7 @@ __global__ __launch_bounds__(kBlock) void k_resid64(const double* __restrict__ p
     rmax = fmax(rmax, mag(r));
     pmax = fmax(pmax, mag(psi[p]));
   }
-  check_and_decide<kBlock>(ctl, part, rmax, pmax, 0);
+  check_and_decide<kBlock>(ctl, part, rmax, pmax, sweeps_done);
 }
 
 __global__ __launch_bounds__(kBlock) void k_refine(double* __restrict__ psi,
@@ -1039,12 +1178,12 @@ int batch_grid(const SorConfig& c, bool mixed, int device) {
 }
 
 hipError_t launch_batch64(const SorConfig& c, const BatchMember* mem, int count, int total_tiles,
-                          int pairs_per_check, BatchCtl* bc, int grid, long long spin_ticks,
-                          hipStream_t st) {
+                          int pairs_per_check, BatchCtl* bc, unsigned int* flags, int grid,
+                          long long spin_ticks, hipStream_t st) {
 #define CAV_L64(TX_, TY_, S_, NT_)                                                              \
   if (c.tx == TX_ && c.ty == TY_ && c.s == S_ && c.nt == NT_) {                                 \
     hipLaunchKernelGGL((k_batch64<TX_, TY_, S_, NT_>), dim3(grid), dim3(NT_), 0, st, mem, count, \
-                       total_tiles, pairs_per_check, bc, spin_ticks);                           \
+                       total_tiles, pairs_per_check, bc, flags, spin_ticks);                    \
     return hipGetLastError();                                                                   \
   }
   CAV_BATCH_CONFIGS_F64(CAV_L64)
@@ -1053,12 +1192,12 @@ hipError_t launch_batch64(const SorConfig& c, const BatchMember* mem, int count,
 }
 
 hipError_t launch_batch_mixed(const SorConfig& c, const BatchMember* mem, int count,
-                              int total_tiles, int inner_pairs, BatchCtl* bc, int grid,
-                              long long spin_ticks, hipStream_t st) {
+                              int total_tiles, int inner_pairs, BatchCtl* bc, unsigned int* flags,
+                              int grid, long long spin_ticks, hipStream_t st) {
 #define CAV_L32(TX_, TY_, S_, NT_)                                                          \
   if (c.tx == TX_ && c.ty == TY_ && c.s == S_ && c.nt == NT_) {                             \
     hipLaunchKernelGGL((k_batch_mixed<TX_, TY_, S_, NT_>), dim3(grid), dim3(NT_), 0, st, mem, \
-                       count, total_tiles, inner_pairs, bc, spin_ticks);                    \
+                       count, total_tiles, inner_pairs, bc, flags, spin_ticks);             \
     return hipGetLastError();                                                               \
   }
   CAV_BATCH_CONFIGS_F32(CAV_L32)
@@ -1069,12 +1208,43 @@ hipError_t launch_batch_mixed(const SorConfig& c, const BatchMember* mem, int co
 int resid_blocks() { return kResidBlocks; }
 
 hipError_t launch_resid64(const double* psi, const double* F, float* R32, float* d32, int n,
-                          int pitch, PoissonCtl* ctl, double* part, hipStream_t st) {
+                          int pitch, PoissonCtl* ctl, double* part, hipStream_t st,
+                          long long sweeps_done) {
   const long long cells = (long long)(n - 2) * (n - 2);
   const int blocks = (int)std::min<long long>(kResidBlocks, (cells + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_resid64, dim3(blocks), dim3(kBlock), 0, st, psi, F, R32, d32, n, pitch,
-                     ctl, part);
+                     ctl, part, sweeps_done);
   return hipGetLastError();
+}
+
+hipError_t launch_mg_residual(const double* psi, const double* F, double* r, int n, int pitch,
+                              double h, const PoissonCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_mg_residual, grid2d(n, n), dim3(kBlock), 0, st, psi, F, r, n, pitch,
+                     1.0 / (0.3 * h * h), ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_mg_restrict(const double* r, int nf, int pitchf, double* Fc, double* Ec,
+                              double* Ecb, int nc, int pitchc, const PoissonCtl* ctl,
+                              hipStream_t st) {
+  const double hc = 1.0 / (nc - 1);
+  const double ratio = (double)(nc - 1) / (double)(nf - 1);
+  hipLaunchKernelGGL(k_mg_restrict, grid2d(nc, nc), dim3(kBlock), 0, st, r, nf, pitchf, Fc, Ec,
+                     Ecb, nc, pitchc, 0.3 * hc * hc * ratio * ratio, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_mg_prolong(const double* Ec, int nc, int pitchc, double* psi, int nf, int pitchf,
+                             const PoissonCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_mg_prolong, grid2d(nf, nf), dim3(kBlock), 0, st, Ec, nc, pitchc, psi, nf,
+                     pitchf, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_sor64_relax(const SorConfig& cfg, const double* psi_in, double* psi_out,
+                              const double* F, int n, int pitch, PoissonCtl* ctl, double relax,
+                              hipStream_t st) {
+  return sor_dispatch<double>(cfg, psi_in, psi_out, F, n, pitch, ctl, nullptr, 0, relax, st);
 }
 
 hipError_t launch_refine(double* psi, const float* d32, int n, int pitch, PoissonCtl* ctl,

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -57,6 +58,20 @@ constexpr double kA54 = 0.386708617503269, kB54 = 0.226007483236906;
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// One level of the multigrid hierarchy (level 0 is the cavity's own grid).
+struct MgLevel {
+  int n = 0, pitch = 0;
+  double h = 0;
+  double* E = nullptr;   // iterate (level 0: psi)
+  double* Eb = nullptr;  // ping-pong partner (level 0: psi_b)
+  double* F = nullptr;   // right-hand side, pre-scaled by 0.3 h^2
+  double* r = nullptr;   // residual in vorticity units (not on the coarsest level)
+};
+
+constexpr int kMgCoarsest = 9;     // levels stop at n <= 9
+constexpr int kMgCoarseSweeps = 24;  // relaxation sweeps on the coarsest level
+constexpr double kMgCoarseRelax = 1.5;
+
 struct Member {
   cavity_params p{};
   int n = 0, pitch = 0;
@@ -82,6 +97,8 @@ struct Member {
   cav::SorConfig cfg32{64, 64, 2, 1024, 0};
   int pairs_per_check = 1;  // FP64: launch pairs between residual checks
   int inner_sweeps = 0;     // mixed: FP32 sweeps per refinement round
+  int solver = CAVITY_SOLVER_SOR;
+  std::vector<MgLevel> mg;  // multigrid hierarchy (allocated for every cavity)
   // host-side state
   long long step = 0;
   double t = 0;
@@ -113,6 +130,7 @@ struct cavity_s {
   int grid = 0;
   cav::BatchMember* d_mem = nullptr;    // device descriptors (workspace)
   cav::BatchCtl* d_bc = nullptr;        // grid barrier (workspace)
+  unsigned int* d_flags = nullptr;      // grid-barrier arrival flags (workspace)
   cav::BatchCtl* host_bc = nullptr;     // pinned readback
   std::vector<cav::BatchMember> h_mem;
   std::vector<cav::PoissonCtl> last_tot;  // totals at the previous readback
@@ -206,8 +224,25 @@ size_t part_doubles(int n) {
   return 2 * (size_t)std::max(cav::sor_max_blocks(n), cav::resid_blocks());
 }
 
+size_t flag_bytes() { return (size_t)cav::kMaxBatchGrid * cav::kFlagStride * sizeof(unsigned int); }
+
 size_t handle_bytes(int count) {
-  return align_up((size_t)count * sizeof(cav::BatchMember)) + align_up(sizeof(cav::BatchCtl));
+  return align_up((size_t)count * sizeof(cav::BatchMember)) + align_up(sizeof(cav::BatchCtl)) +
+         align_up(flag_bytes());
+}
+
+std::vector<int> mg_sizes(int n) {
+  std::vector<int> v{n};
+  while (v.back() > kMgCoarsest) v.push_back((v.back() - 1 + 1) / 2 + 1);
+  return v;
+}
+
+size_t mg_bytes(int n) {
+  const std::vector<int> v = mg_sizes(n);
+  size_t b = align_up((size_t)n * pitch_of(n) * sizeof(double));  // level-0 residual
+  for (size_t l = 1; l < v.size(); ++l)
+    b += 4 * align_up((size_t)v[l] * pitch_of(v[l]) * sizeof(double));
+  return b;
 }
 
 size_t member_bytes(const Member& m) {
@@ -219,6 +254,7 @@ size_t member_bytes(const Member& m) {
   b += align_up(part_doubles(m.n) * sizeof(double));
   b += align_up((size_t)cav::diag_partials(m.n) * 4 * sizeof(double));
   b += align_up(4 * sizeof(double));
+  b += mg_bytes(m.n);
   return b;
 }
 
@@ -246,7 +282,33 @@ void carve(Member& m, char*& cur) {
   m.diag_np = cav::diag_partials(m.n);
   m.diag_partial = reinterpret_cast<double*>(take(align_up((size_t)m.diag_np * 4 * 8)));
   m.diag_out = reinterpret_cast<double*>(take(align_up(4 * sizeof(double))));
+  const std::vector<int> v = mg_sizes(m.n);
+  m.mg.assign(v.size(), MgLevel{});
+  for (size_t l = 0; l < v.size(); ++l) {
+    MgLevel& L = m.mg[l];
+    L.n = v[l];
+    L.pitch = pitch_of(v[l]);
+    L.h = 1.0 / (v[l] - 1);
+    const size_t f = align_up((size_t)L.n * L.pitch * sizeof(double));
+    if (l == 0) {
+      L.E = m.psi;
+      L.Eb = m.psi_b;
+      L.F = m.F;
+      L.r = reinterpret_cast<double*>(take(f));
+    } else {
+      L.E = reinterpret_cast<double*>(take(f));
+      L.Eb = reinterpret_cast<double*>(take(f));
+      L.F = reinterpret_cast<double*>(take(f));
+      L.r = reinterpret_cast<double*>(take(f));
+    }
+  }
 }
+
+// Multigrid smoothing kernels: four-colour sweeps, 2 per launch.
+cav::SorConfig mg_cfg(int n) {
+  return n > 320 ? cav::SorConfig{64, 64, 2, 1024, 0} : cav::SorConfig{32, 32, 2, 256, 0};
+}
+constexpr int kMgNu = 2;   // pre- and post-smoothing sweeps (one launch each)
 
 // ---------------------------------------------------------------------------
 // Poisson solves.  All members listed in `idx` are solved together: their
@@ -254,17 +316,62 @@ void carve(Member& m, char*& cur) {
 // Each solve starts from the psi in Member::psi and leaves its result there;
 // F must already hold the right-hand side.
 // ---------------------------------------------------------------------------
+long long unit_sweeps(const Member& m);
+
 int reset_ctl(cavity_s* h, Member& m) {
   const double tol_hat = m.tol * 0.3 * m.h * m.h;  // (g - psi) = (3 h^2 / 10) r
-  const long long spc = m.mixed ? m.inner_sweeps : 2LL * m.cfg64.s * m.pairs_per_check;
-  HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, m.stall_window, spc,
-                                   h->st));
+  const long long spc = unit_sweeps(m);
+  // multigrid halves the residual every cycle until the rounding floor:
+  // eight cycles without halving mean the floor
+  const long long stall = m.solver == CAVITY_SOLVER_MG ? 8LL * spc : m.stall_window;
+  HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, stall, spc, h->st));
   return CAVITY_OK;
 }
 
-// Sweeps between two residual checks.
+// Sweeps between two residual checks (multigrid: fine-level sweeps of one
+// V-cycle).
 long long unit_sweeps(const Member& m) {
+  if (m.solver == CAVITY_SOLVER_MG) return 2LL * kMgNu;
   return m.mixed ? m.inner_sweeps : 2LL * m.cfg64.s * m.pairs_per_check;
+}
+
+// One V(2,2)-cycle of the compact equation for member m, starting and ending
+// with the iterate in m.psi.  Each smoothing step is one launch of two
+// four-colour Gauss-Seidel sweeps from one buffer of the level to the other,
+// so after pre- and post-smoothing a level's iterate is back in its first
+// buffer; the coarsest level takes an even number of launches.
+int enqueue_vcycle(cavity_s* h, Member& m) {
+  const int L = (int)m.mg.size() - 1;
+  auto E = [&](int l) { return l == 0 ? m.psi : m.mg[l].E; };
+  auto Eb = [&](int l) { return l == 0 ? m.psi_b : m.mg[l].Eb; };
+  auto Fp = [&](int l) { return l == 0 ? m.F : m.mg[l].F; };
+  for (int l = 0; l < L; ++l) {
+    const MgLevel& v = m.mg[l];
+    const MgLevel& c = m.mg[l + 1];
+    HIP_TRY(h, cav::launch_sor64_relax(mg_cfg(v.n), E(l), Eb(l), Fp(l), v.n, v.pitch, m.ctl, 1.0,
+                                       h->st));
+    HIP_TRY(h, cav::launch_mg_residual(Eb(l), Fp(l), v.r, v.n, v.pitch, v.h, m.ctl, h->st));
+    HIP_TRY(h, cav::launch_mg_restrict(v.r, v.n, v.pitch, c.F, c.E, c.Eb, c.n, c.pitch, m.ctl,
+                                       h->st));
+  }
+  {
+    const MgLevel& c = m.mg[L];
+    const cav::SorConfig cc = mg_cfg(c.n);
+    for (int k = 0; k < kMgCoarseSweeps / (2 * cc.s); ++k) {
+      HIP_TRY(h, cav::launch_sor64_relax(cc, E(L), Eb(L), Fp(L), c.n, c.pitch, m.ctl,
+                                         kMgCoarseRelax, h->st));
+      HIP_TRY(h, cav::launch_sor64_relax(cc, Eb(L), E(L), Fp(L), c.n, c.pitch, m.ctl,
+                                         kMgCoarseRelax, h->st));
+    }
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    const MgLevel& v = m.mg[l];
+    const MgLevel& c = m.mg[l + 1];
+    HIP_TRY(h, cav::launch_mg_prolong(E(l + 1), c.n, c.pitch, Eb(l), v.n, v.pitch, m.ctl, h->st));
+    HIP_TRY(h, cav::launch_sor64_relax(mg_cfg(v.n), Eb(l), E(l), Fp(l), v.n, v.pitch, m.ctl, 1.0,
+                                       h->st));
+  }
+  return CAVITY_OK;
 }
 
 // One chunk of work for member m: `units` check groups (FP64: pairs_per_check
@@ -272,7 +379,12 @@ long long unit_sweeps(const Member& m) {
 // Every launch returns at once once the solve has stopped.
 int enqueue_chunk(cavity_s* h, Member& m, int units) {
   for (int u = 0; u < units; ++u) {
-    if (!m.mixed) {
+    if (m.solver == CAVITY_SOLVER_MG) {
+      const int rc = enqueue_vcycle(h, m);
+      if (rc != CAVITY_OK) return rc;
+      HIP_TRY(h, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, m.part,
+                                     h->st, 2LL * kMgNu));
+    } else if (!m.mixed) {
       for (int q = 0; q < m.pairs_per_check; ++q) {
         const int check = (q == m.pairs_per_check - 1) ? 1 : 0;
         HIP_TRY(h, cav::launch_sor64(m.cfg64, m.psi, m.psi_b, m.F, m.n, m.pitch, m.ctl, m.part,
@@ -316,7 +428,9 @@ int read_ctls(cavity_s* h, const std::vector<int>& idx) {
   return CAVITY_OK;
 }
 
-int solve_members(cavity_s* h, const std::vector<int>& idx) {
+// state_solve: the solve produces the state's psi (refresh its FP32 shadow);
+// false for solves into scratch buffers.
+int solve_members(cavity_s* h, const std::vector<int>& idx, bool state_solve = true) {
   int rc;
   for (int k : idx) {
     Member& m = h->m[k];
@@ -361,7 +475,8 @@ int solve_members(cavity_s* h, const std::vector<int>& idx) {
   }
   for (int k : idx) {
     Member& m = h->m[k];
-    if (m.mixed) HIP_TRY(h, cav::launch_shadow(m.psi, m.psi32, m.n, m.pitch, h->st));
+    if (m.mixed && state_solve)
+      HIP_TRY(h, cav::launch_shadow(m.psi, m.psi32, m.n, m.pitch, h->st));
   }
   int worst = CAVITY_OK;
   for (int k : idx) {
@@ -435,7 +550,7 @@ int setup_batch(cavity_s* h) {
                        hipMemcpyHostToDevice));
   const int g = cav::batch_grid(c, h->mixed, h->device);
   if (g <= 0) return fail(CAVITY_EHIP, "occupancy query for the batched kernel failed");
-  h->grid = std::min(g, h->total_tiles);
+  h->grid = std::min(std::min(g, cav::kMaxBatchGrid), h->total_tiles);
   if (h->grid < h->count) h->grid = std::min(g, h->count);
   if (h->grid < h->count)
     return fail(CAVITY_EINVAL, "batch of %d cavities needs at least %d co-resident blocks",
@@ -463,10 +578,11 @@ int enqueue_batch_solve(cavity_s* h) {
   const long long spin = 10LL * 100000000LL;  // 10 s of the 100 MHz wall clock
   if (!h->mixed)
     HIP_TRY(h, cav::launch_batch64(h->bcfg64, h->d_mem, h->count, h->total_tiles, h->b_ppc,
-                                   h->d_bc, h->grid, spin, h->st));
+                                   h->d_bc, h->d_flags, h->grid, spin, h->st));
   else
     HIP_TRY(h, cav::launch_batch_mixed(h->bcfg32, h->d_mem, h->count, h->total_tiles,
-                                       h->b_inner_pairs, h->d_bc, h->grid, spin, h->st));
+                                       h->b_inner_pairs, h->d_bc, h->d_flags, h->grid, spin,
+                                       h->st));
   for (Member& m : h->m)
     if (m.mixed) HIP_TRY(h, cav::launch_shadow(m.psi, m.psi32, m.n, m.pitch, h->st));
   return CAVITY_OK;
@@ -640,6 +756,200 @@ int step_all(cavity_s* h, bool want_diag) {
   return worst;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner.  Every measurement runs on scratch buffers (psi_prev, psi_b, F,
+// w[3], the FP32 fields and the control block between steps), so the state
+// of the simulation is untouched.
+// ---------------------------------------------------------------------------
+struct EventTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool ok = false;
+  EventTimer() { ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess; }
+  ~EventTimer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// Microseconds per sweep of `launches` back-to-back launches of config c.
+int time_sweeps(cavity_s* h, Member& m, const cav::SorConfig& c, bool fp32, int launches,
+                double* us_per_sweep) {
+  EventTimer ev;
+  if (!ev.ok) return fail(CAVITY_EHIP, "hipEventCreate failed");
+  HIP_TRY(h, cav::launch_poisson_rhs(m.w[0], m.F, m.n, m.pitch, m.h, h->st));
+  HIP_TRY(h, cav::launch_copy(m.psi, m.psi_prev, m.n, m.pitch, h->st));
+  HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, -1.0, 1LL << 62, 1LL << 62, 0, h->st));
+  if (fp32) {
+    HIP_TRY(h, cav::launch_resid64(m.psi, m.F, m.R32, m.d32a, m.n, m.pitch, m.ctl, m.part,
+                                   h->st));
+    HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, -1.0, 1LL << 62, 1LL << 62, 0, h->st));
+  }
+  for (int k = -2; k < launches; ++k) {
+    if (k == 0) HIP_TRY(h, hipEventRecord(ev.a, h->st));
+    const bool fwd = (k & 1) == 0;
+    if (fp32)
+      HIP_TRY(h, cav::launch_sor32(c, fwd ? m.d32a : m.d32b, fwd ? m.d32b : m.d32a, m.R32, m.n,
+                                   m.pitch, m.ctl, m.relax, h->st));
+    else
+      HIP_TRY(h, cav::launch_sor64(c, fwd ? m.psi_prev : m.psi_b, fwd ? m.psi_b : m.psi_prev,
+                                   m.F, m.n, m.pitch, m.ctl, m.part, 0, h->st));
+  }
+  HIP_TRY(h, hipEventRecord(ev.b, h->st));
+  HIP_TRY(h, hipEventSynchronize(ev.b));
+  float ms = 0.f;
+  HIP_TRY(h, hipEventElapsedTime(&ms, ev.a, ev.b));
+  *us_per_sweep = 1e3 * ms / ((double)launches * c.s);
+  return CAVITY_OK;
+}
+
+// Wall time of one complete solve of the member's current vorticity from a
+// zero start, on scratch buffers (like cavity_poisson with a given omega).
+int time_solve(cavity_s* h, int idx, double* ms_out) {
+  Member& m = h->m[idx];
+  double* saved_psi = m.psi;
+  const long long saved_total = m.sweeps_total, saved_step = m.sweeps_step;
+  const double saved_est = m.est_sweeps;
+  const int saved_floor = m.floor_step, saved_status = m.status_step;
+  const double saved_resid = m.last_resid;
+  HIP_TRY(h, cav::launch_copy(m.w[0], m.w[3], m.n, m.pitch, h->st));
+  HIP_TRY(h, cav::launch_fill(m.psi_prev, m.n, m.pitch, 0.0, h->st));
+  HIP_TRY(h, cav::launch_poisson_rhs(m.w[3], m.F, m.n, m.pitch, m.h, h->st));
+  HIP_TRY(h, hipStreamSynchronize(h->st));
+  m.psi = m.psi_prev;
+  m.est_sweeps = saved_est;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int rc = solve_members(h, std::vector<int>{idx}, false);
+  (void)hipStreamSynchronize(h->st);
+  const auto t1 = std::chrono::steady_clock::now();
+  m.psi = saved_psi;
+  m.sweeps_total = saved_total;
+  m.sweeps_step = saved_step;
+  m.est_sweeps = saved_est;
+  m.floor_step = saved_floor;
+  m.status_step = saved_status;
+  m.last_resid = saved_resid;
+  if (rc != CAVITY_OK) return rc;
+  *ms_out = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  return CAVITY_OK;
+}
+
+// Microseconds per round of the persistent kernel with config c, over a
+// fixed number of rounds (no member stops early), on scratch descriptors.
+int time_batch(cavity_s* h, const cav::SorConfig& c, int rounds, double* us_per_round) {
+  EventTimer ev;
+  if (!ev.ok) return fail(CAVITY_EHIP, "hipEventCreate failed");
+  const cav::SorConfig saved64 = h->bcfg64, saved32 = h->bcfg32;
+  const int saved_ppc = h->b_ppc, saved_inner = h->b_inner_pairs;
+  if (h->mixed) h->bcfg32 = c; else h->bcfg64 = c;
+  int rc = setup_batch(h);
+  if (rc != CAVITY_OK) return rc;
+  // scratch descriptors: psi -> psi_prev, and the sweep limit ends each
+  // member's solve after `rounds` rounds
+  std::vector<cav::BatchMember> scratch = h->h_mem;
+  for (int k = 0; k < h->count; ++k) {
+    Member& m = h->m[k];
+    scratch[k].psi = m.psi_prev;
+    HIP_TRY(h, cav::launch_copy(m.psi, m.psi_prev, m.n, m.pitch, h->st));
+    HIP_TRY(h, cav::launch_poisson_rhs(m.w[0], m.F, m.n, m.pitch, m.h, h->st));
+  }
+  HIP_TRY(h, hipMemcpy(h->d_mem, scratch.data(), h->count * sizeof(cav::BatchMember),
+                       hipMemcpyHostToDevice));
+  const long long per_round = c.s;
+  h->b_ppc = 1;
+  h->b_inner_pairs = 1;
+  for (Member& m : h->m)
+    HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, -1.0, rounds * per_round, 1LL << 62,
+                                     2 * per_round, h->st));
+  const long long spin = 10LL * 100000000LL;
+  HIP_TRY(h, hipEventRecord(ev.a, h->st));
+  if (h->mixed) {
+    HIP_TRY(h, cav::launch_batch_mixed(c, h->d_mem, h->count, h->total_tiles, 1, h->d_bc,
+                                       h->d_flags, h->grid, spin, h->st));
+  } else {
+    HIP_TRY(h, cav::launch_batch64(c, h->d_mem, h->count, h->total_tiles, 1, h->d_bc,
+                                   h->d_flags, h->grid, spin, h->st));
+  }
+  HIP_TRY(h, hipEventRecord(ev.b, h->st));
+  HIP_TRY(h, hipEventSynchronize(ev.b));
+  float ms = 0.f;
+  HIP_TRY(h, hipEventElapsedTime(&ms, ev.a, ev.b));
+  // mixed rounds: residual + 2 FP32 launches + refinement; FP64: 2 launches + decision
+  const int launches_per_round = 2;
+  const long long done_rounds = h->mixed ? (rounds * per_round) / (2 * c.s) + 1
+                                         : (rounds * per_round) / (2 * c.s);
+  *us_per_round = 1e3 * ms / ((double)std::max<long long>(1, done_rounds) * launches_per_round);
+  h->bcfg64 = saved64;
+  h->bcfg32 = saved32;
+  h->b_ppc = saved_ppc;
+  h->b_inner_pairs = saved_inner;
+  rc = setup_batch(h);  // restores the real descriptors
+  if (rc != CAVITY_OK) return rc;
+  return collect_totals(h, false);
+}
+
+std::string arch_name(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string tune_key(cavity_s* h, int idx) {
+  char buf[512];
+  if (idx >= 0) {
+    snprintf(buf, sizeof buf, "%s|n=%d|prec=%d|solver=%d|batch=0", arch_name(h->device).c_str(),
+             h->m[idx].n, h->m[idx].mixed ? 1 : 0, h->m[idx].solver);
+    return buf;
+  }
+  std::string k = arch_name(h->device) + "|prec=" + (h->mixed ? "1" : "0") + "|batch=";
+  for (const Member& m : h->m) k += std::to_string(m.n) + ",";
+  return k;
+}
+
+bool cache_lookup(const char* path, const std::string& key, cavity_tuning* t) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  const std::string pre = "{\"key\": \"" + key + "\", ";
+  while (fgets(line, sizeof line, f)) {
+    if (strncmp(line, pre.c_str(), pre.size()) != 0) continue;
+    cavity_tuning r{};
+    const int got = sscanf(line + pre.size(),
+                           "\"tile_x\": %d, \"tile_y\": %d, \"sweeps_per_launch\": %d, "
+                           "\"threads\": %d, \"tile_x32\": %d, \"tile_y32\": %d, "
+                           "\"sweeps_per_launch32\": %d, \"threads32\": %d, "
+                           "\"check_every\": %d, \"inner_sweeps\": %d, \"xcd_bands\": %d, "
+                           "\"solver\": %d, \"sor_omega\": %lf",
+                           &r.tile_x, &r.tile_y, &r.sweeps_per_launch, &r.threads, &r.tile_x32,
+                           &r.tile_y32, &r.sweeps_per_launch32, &r.threads32, &r.check_every,
+                           &r.inner_sweeps, &r.xcd_bands, &r.solver, &r.sor_omega);
+    if (got == 13) {
+      *t = r;
+      found = true;  // the last matching line wins
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const cavity_tuning& t) {
+  if (!path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f,
+          "{\"key\": \"%s\", \"tile_x\": %d, \"tile_y\": %d, \"sweeps_per_launch\": %d, "
+          "\"threads\": %d, \"tile_x32\": %d, \"tile_y32\": %d, \"sweeps_per_launch32\": %d, "
+          "\"threads32\": %d, \"check_every\": %d, \"inner_sweeps\": %d, "
+          "\"xcd_bands\": %d, \"solver\": %d, \"sor_omega\": %.17g}\n",
+          key.c_str(), t.tile_x, t.tile_y, t.sweeps_per_launch, t.threads, t.tile_x32,
+          t.tile_y32, t.sweeps_per_launch32, t.threads32, t.check_every, t.inner_sweeps,
+          t.xcd_bands, t.solver, t.sor_omega);
+  fclose(f);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -707,13 +1017,16 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
   h->d_mem = reinterpret_cast<cav::BatchMember*>(cur);
   cur += align_up((size_t)count * sizeof(cav::BatchMember));
   h->d_bc = reinterpret_cast<cav::BatchCtl*>(cur);
+  cur += align_up(sizeof(cav::BatchCtl));
+  h->d_flags = reinterpret_cast<unsigned int*>(cur);
   h->w0_base = h->m[0].w[0];
 
   auto bail = [&](int rc) {
     cavity_destroy(h);
     return rc;
   };
-  if (cav::launch_zero(h->d_bc, sizeof(cav::BatchCtl), h->st) != hipSuccess)
+  if (cav::launch_zero(h->d_bc, sizeof(cav::BatchCtl), h->st) != hipSuccess ||
+      cav::launch_zero(h->d_flags, flag_bytes(), h->st) != hipSuccess)
     return bail(fail(CAVITY_EHIP, "zero fill failed"));
   for (Member& m : h->m) {
     if (cav::launch_zero(m.ctl, sizeof(cav::PoissonCtl), h->st) != hipSuccess)
@@ -852,7 +1165,7 @@ int cavity_poisson(cavity_t h, int32_t idx, const double* d_omega, double* d_psi
     if ((rc = enqueue_rhs_and_walls_prep(h, m, m.w[0])) != CAVITY_OK) return rc;
   }
   const long long before = m.sweeps_total;
-  rc = solve_members(h, std::vector<int>{idx});
+  rc = solve_members(h, std::vector<int>{idx}, d_omega == nullptr);
   double* result = m.psi;
   m.psi = saved_psi;
   m.psi_b = saved_b;
@@ -960,6 +1273,7 @@ int cavity_get_tuning(cavity_t h, int32_t idx, cavity_tuning* t) {
   t->check_every = (int32_t)(2LL * m.cfg64.s * m.pairs_per_check);
   t->inner_sweeps = m.inner_sweeps;
   t->xcd_bands = m.cfg64.xcd_bands;
+  t->solver = m.solver;
   t->sor_omega = m.relax;
   return CAVITY_OK;
 }
@@ -999,12 +1313,128 @@ int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t) {
     return fail(CAVITY_EINVAL, "check_every and inner_sweeps must be >= 1");
   if (!(t->sor_omega > 0.0 && t->sor_omega < 2.0))
     return fail(CAVITY_EINVAL, "sor_omega must lie in (0, 2)");
+  if (t->solver != CAVITY_SOLVER_SOR && t->solver != CAVITY_SOLVER_MG)
+    return fail(CAVITY_EINVAL, "unknown solver %d", t->solver);
   Member& m = h->m[idx];
+  if (t->solver == CAVITY_SOLVER_MG && (m.mixed || h->exec != CAVITY_EXEC_STREAM))
+    return fail(CAVITY_EINVAL, "the multigrid solver runs FP64 cavities in stream execution");
+  m.solver = t->solver;
   m.cfg64 = c64;
   m.cfg32 = c32;
   m.relax = t->sor_omega;
   set_schedule(m, t->check_every, t->inner_sweeps);
   m.est_sweeps = 0;
+  return CAVITY_OK;
+}
+
+int cavity_autotune(cavity_t h, int32_t idx, const char* cache_path, cavity_tuning* chosen) {
+  if (!h) return fail(CAVITY_EINVAL, "null handle");
+  if (h->poisoned) return fail(CAVITY_ESTATE, "handle poisoned by an earlier failure");
+  if (idx < -1 || idx >= h->count) return fail(CAVITY_EINVAL, "idx %d out of range", idx);
+  HIP_TRY(h, hipSetDevice(h->device));
+  int rc;
+  const std::string key = tune_key(h, idx);
+  cavity_tuning t{};
+  if (cache_lookup(cache_path, key, &t)) {
+    if ((rc = cavity_set_tuning(h, idx, &t)) != CAVITY_OK) return rc;
+    if (chosen) *chosen = t;
+    return CAVITY_OK;
+  }
+  if ((rc = cavity_get_tuning(h, idx, &t)) != CAVITY_OK) return rc;
+  struct Cand { int tx, ty, s, nt, xcd; };
+  static const Cand k64[] = {{32, 32, 1, 256, 0}, {32, 32, 2, 256, 0}, {64, 32, 2, 512, 0},
+                             {64, 64, 1, 1024, 0}, {64, 64, 2, 1024, 0}, {64, 64, 3, 1024, 0},
+                             {64, 64, 4, 1024, 0}, {128, 32, 2, 1024, 0}, {96, 64, 2, 1024, 0}};
+  static const Cand k32[] = {{32, 32, 1, 256, 0}, {32, 32, 2, 256, 0}, {64, 32, 2, 512, 0},
+                             {64, 64, 2, 512, 0}, {64, 64, 2, 1024, 0}, {64, 64, 4, 1024, 0},
+                             {128, 64, 3, 1024, 0}, {128, 64, 4, 1024, 0}, {96, 96, 3, 1024, 0}};
+  if (idx >= 0) {
+    Member& m = h->m[idx];
+    // 1. tile shape, sweeps per launch and tile order, by sweep time
+    for (int pass = 0; pass < (m.mixed ? 2 : 1); ++pass) {
+      const bool fp32 = pass == 1;
+      double best = 1e300;
+      cav::SorConfig bc = fp32 ? m.cfg32 : m.cfg64;
+      const long long cells = (long long)m.n * m.n;
+      const int launches = (int)std::max<long long>(8, std::min<long long>(400, 40000000LL / cells));
+      for (const Cand& c0 : (fp32 ? k32 : k64)) {
+        for (int xcd = 0; xcd < 2; ++xcd) {
+          const cav::SorConfig c{c0.tx, c0.ty, c0.s, c0.nt, xcd};
+          const int tiles = ((m.n + c.tx - 1) / c.tx) * ((m.n + c.ty - 1) / c.ty);
+          if (xcd && tiles % 8 != 0) continue;
+          if (!cav::sor_config_supported(c, fp32)) continue;
+          double us = 0;
+          if ((rc = time_sweeps(h, m, c, fp32, launches + (launches & 1), &us)) != CAVITY_OK)
+            return rc;
+          if (us < best) {
+            best = us;
+            bc = c;
+          }
+        }
+      }
+      if (fp32) m.cfg32 = bc; else m.cfg64 = bc;
+    }
+    // 2. sweep schedule, by the time of complete solves of the current state
+    const int u64 = 2 * m.cfg64.s;
+    const int u32 = 2 * m.cfg32.s;
+    int best_ce = 2 * m.cfg64.s * m.pairs_per_check, best_in = m.inner_sweeps;
+    double best_ms = 1e300;
+    if (m.solver == CAVITY_SOLVER_MG) {
+      // multigrid checks after every V-cycle; nothing to schedule
+    } else if (!m.mixed) {
+      for (int ce : {8, 16, 32, 64, 128}) {
+        if (ce < u64) continue;
+        set_schedule(m, ce, best_in);
+        double ms = 0;
+        if ((rc = time_solve(h, idx, &ms)) != CAVITY_OK) return rc;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_ce = ce;
+        }
+      }
+    } else {
+      for (double f : {0.5, 1.0, 1.5, 2.0, 3.0}) {
+        const int in = std::max(u32, (int)std::ceil(f * (m.n - 1)));
+        set_schedule(m, best_ce, in);
+        double ms = 0;
+        if ((rc = time_solve(h, idx, &ms)) != CAVITY_OK) return rc;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_in = in;
+        }
+      }
+    }
+    set_schedule(m, best_ce, best_in);
+    m.est_sweeps = 0;
+    destroy_graphs(h);
+    if ((rc = cavity_get_tuning(h, idx, &t)) != CAVITY_OK) return rc;
+  } else {
+    // batched kernel: tile shape by the time per persistent round
+    const bool mixed = h->mixed;
+    double best = 1e300;
+    cav::SorConfig bc = mixed ? h->bcfg32 : h->bcfg64;
+    for (const Cand& c0 : (mixed ? k32 : k64)) {
+      const cav::SorConfig c{c0.tx, c0.ty, c0.s, c0.nt, 0};
+      if (!cav::batch_config_supported(c, mixed)) continue;
+      double us = 0;
+      if ((rc = time_batch(h, c, 48 * 2, &us)) != CAVITY_OK) return rc;
+      const double per_sweep = us / c.s;
+      if (per_sweep < best) {
+        best = per_sweep;
+        bc = c;
+      }
+    }
+    if (mixed) h->bcfg32 = bc; else h->bcfg64 = bc;
+    h->b_ppc = std::max(1, 32 / (2 * h->bcfg64.s));
+    int inner = 0;
+    for (const Member& m : h->m) inner = std::max(inner, m.inner_sweeps);
+    h->b_inner_pairs = std::max(1, (inner + 2 * h->bcfg32.s - 1) / (2 * h->bcfg32.s));
+    if ((rc = setup_batch(h)) != CAVITY_OK) return rc;
+    if ((rc = cavity_get_tuning(h, -1, &t)) != CAVITY_OK) return rc;
+  }
+  if ((rc = collect_totals(h, false)) != CAVITY_OK) return rc;
+  cache_store(cache_path, key, t);
+  if (chosen) *chosen = t;
   return CAVITY_OK;
 }
 
@@ -1021,9 +1451,12 @@ int cavity_set_exec(cavity_t h, int32_t mode) {
     return fail(CAVITY_EINVAL, "unknown execution mode %d", mode);
   HIP_TRY(h, hipSetDevice(h->device));
   if (mode != CAVITY_EXEC_STREAM) {
-    for (const Member& m : h->m)
+    for (const Member& m : h->m) {
       if (m.mixed != h->mixed)
         return fail(CAVITY_EINVAL, "batched execution needs one precision for all cavities");
+      if (m.solver != CAVITY_SOLVER_SOR)
+        return fail(CAVITY_EINVAL, "batched execution runs the SOR solver only");
+    }
     int rc = setup_batch(h);
     if (rc != CAVITY_OK) return rc;
     rc = collect_totals(h, false);

@@ -55,13 +55,14 @@ def test_workspace_bytes_scales_with_grid(binding):
     P = binding.Params
     small = binding.cavity_workspace_bytes([P(n=64).to_c()])
     big = binding.cavity_workspace_bytes([P(n=1024).to_c()])
-    assert big > 200 * small / 2
+    assert big > 20 * small
     # eight FP64 fields of 1024 x 1024 at least
     assert big >= 8 * 1024 * 1024 * 8
     mixed = binding.cavity_workspace_bytes([P(n=1024, precision=binding.CAVITY_MIXED).to_c()])
     assert mixed >= big + 3 * 1024 * 1024 * 4
     two = binding.cavity_workspace_bytes([P(n=64).to_c(), P(n=1024).to_c()])
-    assert abs(two - (small + big)) <= 1024   # one shared handle area instead of two
+    # one shared handle area (descriptors, barrier flags) instead of two
+    assert small + big - 600 * 1024 <= two < small + big
 
 
 @pytest.mark.parametrize("kw,msg", [

@@ -57,3 +57,21 @@ def test_mixed_step_error_vs_fp64_oracle(cm, n, re, steps):
           f"sweeps/step={st['sweeps_last_step']}")
     assert st["status"] == 0
     assert ew <= bound and ep <= bound and ek <= bound, (ep, ew, ek, bound)
+
+
+def test_scratch_solve_leaves_mixed_state_alone(cm):
+    """A Poisson solve of a caller-given vorticity must not disturb the state."""
+    n, re, steps = 97, 2000.0, 6
+    print("[mixed scratch solve]", flush=True)
+    a = cm.Cavity(cm.Params(n=n, re=re, precision=cm.CAVITY_MIXED))
+    b = cm.Cavity(cm.Params(n=n, re=re, precision=cm.CAVITY_MIXED))
+    a.step(3, want_stats=False)
+    b.step(3, want_stats=False)
+    b.poisson(0, np.random.default_rng(0).standard_normal((n, n)))
+    a.step(steps - 3, want_stats=False)
+    b.step(steps - 3, want_stats=False)
+    pa, wa, _, _ = a.fields()
+    pb, wb, _, _ = b.fields()
+    a.close()
+    b.close()
+    assert np.array_equal(pa, pb) and np.array_equal(wa, wb)
