@@ -6,11 +6,13 @@
 A step is one SSPRK(5,4) step of the whole hot path (five stages, each with
 transport RHS + stage combination, compact-Poisson SOR solve to tolerance,
 Thom walls).  The headline workload is the 1024 x 1024 cavity at Re = 1e4,
-started from rest, FP64, Poisson tolerance 1e-10.  Inputs are resident in HBM
-when timing starts.  Extras (same JSON line): the mixed-precision 1024 x 1024
-Re = 3e4 cavity, and the six-cavity Reynolds sweep (256^2 ... 1024^2) batched
-in one persistent launch per stage vs the same cavities run one by one.
-Prints one JSON line.
+started from rest, FP64, Poisson tolerance 1e-10, solved by the paper's
+relaxation (four-colour SOR).  Inputs are resident in HBM when timing starts.
+Extras (same JSON line): the same workload with the multigrid solver and in
+persistent execution; the mixed-precision 1024 x 1024 Re = 3e4 cavity; the
+4096 x 4096 Re = 3e4 noise-start cavity (mixed SOR, and FP64 multigrid); the
+six-cavity Reynolds sweep (256^2 ... 1024^2) batched in one persistent launch
+per stage (hipGraph) vs the same cavities run one by one.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -105,7 +107,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cavity1024_re1e4_fp64")
-    ap.add_argument("--exec", default="persistent", choices=sorted(EXEC))
+    ap.add_argument("--exec", default="stream", choices=sorted(EXEC))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed and batched lines")
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -118,18 +120,27 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_0809_3098_amd.cavity import CAVITY_FP64, CAVITY_MIXED, Cavity, Params
+    from paper_0809_3098_amd import inputs
+    from paper_0809_3098_amd.cavity import (CAVITY_FP64, CAVITY_MIXED, CAVITY_SOLVER_MG, Cavity,
+                                            Params)
     from paper_0809_3098_amd.workloads import WORKLOADS
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
 
-    def single(name, steps, warmup, mode):
+    def single(name, steps, warmup, mode, solver=0, precision=None):
         wl = WORKLOADS[name]
         prec = CAVITY_MIXED if wl["precision"] == "mixed" else CAVITY_FP64
+        if precision is not None:
+            prec = precision
+        omega0 = None
+        if wl["init"] == "noise":
+            omega0 = [inputs.noise_omega0(wl["n"], wl["noise_amplitude"], wl["noise_seed"])]
         cav = Cavity(Params(n=wl["n"], re=wl["re"], poisson_tol=wl["tol"], precision=prec),
-                     device="cuda:0", stream=stream)
+                     device="cuda:0", stream=stream, omega0=omega0)
+        if solver:
+            cav.set_tuning(solver=solver)
         cav.set_exec(EXEC[mode])
         el, stats = _timed_steps(torch, cav, steps, warmup)
         n = wl["n"]
@@ -137,7 +148,10 @@ def main():
                "ms_per_step": round(1e3 * el / max(steps, 1), 3),
                "sweeps_per_stage": stats[0]["sweeps_last_step"] / 5 if stats else None,
                "floor_limited_last_step": stats[0]["floor_limited"] if stats else None,
-               "exec": mode}
+               "domega_inf_over_dt": stats[0]["domega_inf_over_dt"] if stats else None,
+               "steps": steps, "exec": mode,
+               "solver": "multigrid" if solver else "sor",
+               "precision": "mixed" if prec == CAVITY_MIXED else "fp64"}
         return cav, prec, out
 
     # ---- headline: FP64 1024^2
@@ -150,12 +164,29 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        # same workload, multigrid solver (same compact equation, same tolerance)
+        cmg, _, mg = single(args.workload, args.steps, args.warmup, "stream", CAVITY_SOLVER_MG)
+        mg["vcycles_per_stage"] = mg["sweeps_per_stage"] / 4 if mg["sweeps_per_stage"] else None
+        cmg.close()
+        extras["multigrid_1024_re1e4_fp64"] = mg
+        # the persistent-kernel execution of the headline workload
+        cp, _, pers = single(args.workload, args.extra_steps, 1, "persistent")
+        cp.close()
+        extras["persistent_1024_re1e4_fp64"] = pers
         # mixed + refinement at 1024^2, Re 3e4
         cavm, _, mixed = single("cavity1024_re3e4_mixed", args.extra_steps, 1, args.exec)
         mixed["roofline_fp32_sweep"] = _sweep_roofline(torch, cavm, stream, args.relax_launches,
                                                        1, "cavity1024_re3e4_mixed:fp32")
         cavm.close()
         extras["mixed_1024_re3e4"] = mixed
+        # 4096^2, Re 3e4, noise start: mixed SOR (the configuration) and FP64 multigrid
+        c4, _, m4 = single("cavity4096_re3e4_mixed_noise", 1, 0, "stream")
+        c4.close()
+        extras["cavity4096_re3e4_noise_mixed_sor"] = m4
+        c4, _, g4 = single("cavity4096_re3e4_mixed_noise", args.extra_steps, 1, "stream",
+                           CAVITY_SOLVER_MG, CAVITY_FP64)
+        c4.close()
+        extras["cavity4096_re3e4_noise_fp64_multigrid"] = g4
         # batched six-cavity Reynolds sweep vs one by one
         b = WORKLOADS["re_sweep6"]
         cells = sum(m * m for _, m in b["members"])

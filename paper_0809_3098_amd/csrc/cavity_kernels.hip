@@ -355,24 +355,27 @@ __device__ inline int load_state(const PoissonCtl* c) {
 // Grid barrier.  Every block stores the new generation in its own arrival
 // flag (one 128-byte line each, so arrivals never contend); the threads of
 // block 0 wait for all flags in parallel and then release the generation in
-// `go`, which the other blocks wait for.  Returns false (and sets bc->error)
-// if a wait exceeds spin_ticks of the 100 MHz wall clock, so a grid that is
-// not co-resident ends with an error instead of hanging.
+// `go`, which the other blocks wait for.  Waits poll with relaxed atomic
+// loads and order memory with one fence after the wait succeeds: an acquire
+// on every poll would invalidate caches that blocks still computing rely on.
+// Returns false (and sets bc->error) if a wait exceeds spin_ticks of the
+// 100 MHz wall clock, so a grid that is not co-resident ends with an error
+// instead of hanging.
 __device__ bool grid_sync(BatchCtl* bc, unsigned int* flags, unsigned int nb, unsigned int& gen,
                           long long spin_ticks) {
   __shared__ int s_ok;
   __syncthreads();
   gen += 1u;
   if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_store(&flags[blockIdx.x * kFlagStride], gen, __ATOMIC_RELEASE,
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&flags[blockIdx.x * kFlagStride], gen, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
   int ok = 1;
   if (blockIdx.x == 0) {
     const long long t0 = wall_clock64();
     for (unsigned int b = threadIdx.x; b < nb && ok; b += blockDim.x) {
-      while (__hip_atomic_load(&flags[b * kFlagStride], __ATOMIC_ACQUIRE,
+      while (__hip_atomic_load(&flags[b * kFlagStride], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT) != gen) {
         __builtin_amdgcn_s_sleep(1);
         if (__hip_atomic_load(&bc->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
@@ -385,15 +388,15 @@ __device__ bool grid_sync(BatchCtl* bc, unsigned int* flags, unsigned int nb, un
     ok = __syncthreads_and(ok);
     if (threadIdx.x == 0) {
       if (ok) {
-        __threadfence();
-        __hip_atomic_store(&bc->go, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_store(&bc->go, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         __hip_atomic_store(&bc->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   } else if (threadIdx.x == 0) {
     const long long t0 = wall_clock64();
-    while (__hip_atomic_load(&bc->go, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != gen) {
+    while (__hip_atomic_load(&bc->go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gen) {
       __builtin_amdgcn_s_sleep(1);
       if (__hip_atomic_load(&bc->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
           wall_clock64() - t0 > spin_ticks) {
@@ -404,7 +407,7 @@ __device__ bool grid_sync(BatchCtl* bc, unsigned int* flags, unsigned int nb, un
     }
   }
   if (threadIdx.x == 0) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();
