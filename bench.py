@@ -113,6 +113,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--relax-launches", type=int, default=200)
     ap.add_argument("--extra-steps", type=int, default=5)
+    ap.add_argument("--log-run", default=None, metavar="JSONL",
+                    help="instead of the bench: run the 4096^2 Re 3e4 noise-start cavity "
+                         "(mixed, multigrid) for --log-steps steps, one monitor line per step")
+    ap.add_argument("--log-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): every workload here is "
@@ -128,6 +132,28 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+
+    if args.log_run:
+        wl = WORKLOADS["cavity4096_re3e4_mixed_noise"]
+        w0 = inputs.noise_omega0(wl["n"], wl["noise_amplitude"], wl["noise_seed"])
+        cav = Cavity(Params(n=wl["n"], re=wl["re"], poisson_tol=wl["tol"],
+                            precision=CAVITY_MIXED), device="cuda:0", stream=stream,
+                     omega0=[w0])
+        cav.set_tuning(solver=CAVITY_SOLVER_MG)
+        t0 = time.perf_counter()
+        with open(args.log_run, "w") as f:
+            for k in range(args.log_steps):
+                st = cav.step(1)[0]
+                rec = {key: st[key] for key in ("step", "t", "res_psi", "res_omega",
+                                                "domega_inf_over_dt", "ke", "last_resid_inf",
+                                                "sweeps_last_step", "floor_limited", "status")}
+                rec["wall_s"] = round(time.perf_counter() - t0, 3)
+                f.write(json.dumps(rec) + "\n")
+                if (k + 1) % 100 == 0:
+                    f.flush()
+                    print(json.dumps(rec), flush=True)
+        cav.close()
+        return
 
     def single(name, steps, warmup, mode, solver=0, precision=None):
         wl = WORKLOADS[name]

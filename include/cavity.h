@@ -216,8 +216,9 @@ typedef struct cavity_tuning {
  *                      Gauss-Seidel smoothing with the same sweep kernel,
  *                      the compact operator rediscretised on coarser grids
  *                      (m intervals -> ceil(m/2); non-nested levels use
- *                      bilinear transfers in physical coordinates); FP64
- *                      cavities in CAVITY_EXEC_STREAM only
+ *                      bilinear transfers in physical coordinates).  In
+ *                      CAVITY_MIXED each refinement round is one FP32
+ *                      V-cycle on the correction.  CAVITY_EXEC_STREAM only
  */
 enum cavity_solver { CAVITY_SOLVER_SOR = 0, CAVITY_SOLVER_MG = 1 };
 

@@ -160,12 +160,20 @@ hipError_t launch_resid64(const double* psi, const double* F, float* R32, float*
 // Multigrid: residual in vorticity units, restriction to the next coarser
 // level (also zeroing its iterate), prolongation-and-correct, and a sweep
 // launch with an explicit relaxation parameter (no residual check).
+// (FP64 for the FP64 solver; FP32 for the correction cycles of mixed mode.)
 hipError_t launch_mg_residual(const double* psi, const double* F, double* r, int n, int pitch,
+                              double h, const PoissonCtl* ctl, hipStream_t st);
+hipError_t launch_mg_residual(const float* psi, const float* F, float* r, int n, int pitch,
                               double h, const PoissonCtl* ctl, hipStream_t st);
 hipError_t launch_mg_restrict(const double* r, int nf, int pitchf, double* Fc, double* Ec,
                               double* Ecb, int nc, int pitchc, const PoissonCtl* ctl,
                               hipStream_t st);
+hipError_t launch_mg_restrict(const float* r, int nf, int pitchf, float* Fc, float* Ec,
+                              float* Ecb, int nc, int pitchc, const PoissonCtl* ctl,
+                              hipStream_t st);
 hipError_t launch_mg_prolong(const double* Ec, int nc, int pitchc, double* psi, int nf,
+                             int pitchf, const PoissonCtl* ctl, hipStream_t st);
+hipError_t launch_mg_prolong(const float* Ec, int nc, int pitchc, float* psi, int nf,
                              int pitchf, const PoissonCtl* ctl, hipStream_t st);
 hipError_t launch_sor64_relax(const SorConfig& cfg, const double* psi_in, double* psi_out,
                               const double* F, int n, int pitch, PoissonCtl* ctl, double relax,

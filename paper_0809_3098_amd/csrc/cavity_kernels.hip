@@ -601,10 +601,11 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
 // ---------------------------------------------------------------------------
 // r = (g - psi) / (0.3 h^2): the residual of the compact equation in
 // vorticity units (zero on walls).
-__global__ __launch_bounds__(kBlock) void k_mg_residual(const double* __restrict__ psi,
-                                                        const double* __restrict__ F,
-                                                        double* __restrict__ r, int n, int pitch,
-                                                        double inv03h2,
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_residual(const T* __restrict__ psi,
+                                                        const T* __restrict__ F,
+                                                        T* __restrict__ r, int n, int pitch,
+                                                        T inv03h2,
                                                         const PoissonCtl* __restrict__ ctl) {
   if (ctl->state != SOLVE_RUN) return;
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -612,33 +613,33 @@ __global__ __launch_bounds__(kBlock) void k_mg_residual(const double* __restrict
   if (i >= n || j >= n) return;
   const size_t p = (size_t)j * pitch + i;
   if (i == 0 || j == 0 || i == n - 1 || j == n - 1) {
-    r[p] = 0.0;
+    r[p] = T(0);
     return;
   }
-  const double s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pitch] + psi[p - pitch]);
-  const double sd = (psi[p + pitch + 1] + psi[p + pitch - 1]) +
-                    (psi[p - pitch + 1] + psi[p - pitch - 1]);
-  const double g = fma(0.2, s4, fma(0.05, sd, F[p]));
+  const T s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pitch] + psi[p - pitch]);
+  const T sd = (psi[p + pitch + 1] + psi[p + pitch - 1]) + (psi[p - pitch + 1] + psi[p - pitch - 1]);
+  const T g = fma_t(T(0.2), s4, fma_t(T(0.05), sd, F[p]));
   r[p] = (g - psi[p]) * inv03h2;
 }
 
 // Coarse right-hand side F_c = 0.3 h_c^2 R r and a zero coarse iterate (both
 // ping-pong buffers, walls included).
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(const double* __restrict__ r, int nf,
-                                                        int pitchf, double* __restrict__ Fc,
-                                                        double* __restrict__ Ec,
-                                                        double* __restrict__ Ecb, int nc,
-                                                        int pitchc, double scale,
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(const T* __restrict__ r, int nf,
+                                                        int pitchf, T* __restrict__ Fc,
+                                                        T* __restrict__ Ec,
+                                                        T* __restrict__ Ecb, int nc,
+                                                        int pitchc, T scale,
                                                         const PoissonCtl* __restrict__ ctl) {
   if (ctl->state != SOLVE_RUN) return;
   const int I = blockIdx.x * 64 + (threadIdx.x & 63);
   const int J = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (I >= nc || J >= nc) return;
   const size_t pc = (size_t)J * pitchc + I;
-  Ec[pc] = 0.0;
-  Ecb[pc] = 0.0;
+  Ec[pc] = T(0);
+  Ecb[pc] = T(0);
   if (I == 0 || J == 0 || I == nc - 1 || J == nc - 1) {
-    Fc[pc] = 0.0;
+    Fc[pc] = T(0);
     return;
   }
   const long long mf = nf - 1, mc = nc - 1;
@@ -646,26 +647,27 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(const double* __restrict
   const int i1 = min(nf - 2, (int)(((I + 1) * mf + mc - 1) / mc) - 1);
   const int j0 = max(1, (int)(((J - 1) * mf) / mc) + 1);
   const int j1 = min(nf - 2, (int)(((J + 1) * mf + mc - 1) / mc) - 1);
-  const double invmf = 1.0 / (double)mf;
-  double sum = 0.0;
+  const T invmf = T(1) / (T)mf;
+  T sum = T(0);
   for (int j = j0; j <= j1; ++j) {
     const long long dj = (long long)j * mc - (long long)J * mf;
-    const double wy = (double)(mf - (dj < 0 ? -dj : dj)) * invmf;
-    if (wy <= 0.0) continue;
-    double row = 0.0;
+    const T wy = (T)(mf - (dj < 0 ? -dj : dj)) * invmf;
+    if (wy <= T(0)) continue;
+    T row = T(0);
     for (int i = i0; i <= i1; ++i) {
       const long long di = (long long)i * mc - (long long)I * mf;
-      const double wx = (double)(mf - (di < 0 ? -di : di)) * invmf;
-      if (wx > 0.0) row = fma(wx, r[(size_t)j * pitchf + i], row);
+      const T wx = (T)(mf - (di < 0 ? -di : di)) * invmf;
+      if (wx > T(0)) row = fma_t(wx, r[(size_t)j * pitchf + i], row);
     }
-    sum = fma(wy, row, sum);
+    sum = fma_t(wy, row, sum);
   }
   Fc[pc] = scale * sum;
 }
 
 // psi_f += P E_c (bilinear interpolation of the coarse correction).
-__global__ __launch_bounds__(kBlock) void k_mg_prolong(const double* __restrict__ Ec, int nc,
-                                                       int pitchc, double* __restrict__ psi,
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(const T* __restrict__ Ec, int nc,
+                                                       int pitchc, T* __restrict__ psi,
                                                        int nf, int pitchf,
                                                        const PoissonCtl* __restrict__ ctl) {
   if (ctl->state != SOLVE_RUN) return;
@@ -675,12 +677,12 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(const double* __restrict_
   const long long mf = nf - 1, mc = nc - 1;
   const int I = (int)(((long long)i * mc) / mf);
   const int J = (int)(((long long)j * mc) / mf);
-  const double ti = (double)((long long)i * mc - (long long)I * mf) / (double)mf;
-  const double tj = (double)((long long)j * mc - (long long)J * mf) / (double)mf;
+  const T ti = (T)((long long)i * mc - (long long)I * mf) / (T)mf;
+  const T tj = (T)((long long)j * mc - (long long)J * mf) / (T)mf;
   const size_t c = (size_t)J * pitchc + I;
-  const double lo = fma(ti, Ec[c + 1] - Ec[c], Ec[c]);
-  const double hi = fma(ti, Ec[c + pitchc + 1] - Ec[c + pitchc], Ec[c + pitchc]);
-  psi[(size_t)j * pitchf + i] += fma(tj, hi - lo, lo);
+  const T lo = fma_t(ti, Ec[c + 1] - Ec[c], Ec[c]);
+  const T hi = fma_t(ti, Ec[c + pitchc + 1] - Ec[c + pitchc], Ec[c + pitchc]);
+  psi[(size_t)j * pitchf + i] += fma_t(tj, hi - lo, lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -1220,28 +1222,57 @@ hipError_t launch_resid64(const double* psi, const double* F, float* R32, float*
   return hipGetLastError();
 }
 
-hipError_t launch_mg_residual(const double* psi, const double* F, double* r, int n, int pitch,
-                              double h, const PoissonCtl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_mg_residual, grid2d(n, n), dim3(kBlock), 0, st, psi, F, r, n, pitch,
-                     1.0 / (0.3 * h * h), ctl);
+template <typename T>
+hipError_t mg_residual(const T* psi, const T* F, T* r, int n, int pitch, double h,
+                       const PoissonCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_mg_residual<T>, grid2d(n, n), dim3(kBlock), 0, st, psi, F, r, n, pitch,
+                     (T)(1.0 / (0.3 * h * h)), ctl);
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t mg_restrict(const T* r, int nf, int pitchf, T* Fc, T* Ec, T* Ecb, int nc, int pitchc,
+                       const PoissonCtl* ctl, hipStream_t st) {
+  const double hc = 1.0 / (nc - 1);
+  const double ratio = (double)(nc - 1) / (double)(nf - 1);
+  hipLaunchKernelGGL(k_mg_restrict<T>, grid2d(nc, nc), dim3(kBlock), 0, st, r, nf, pitchf, Fc, Ec,
+                     Ecb, nc, pitchc, (T)(0.3 * hc * hc * ratio * ratio), ctl);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_prolong(const T* Ec, int nc, int pitchc, T* psi, int nf, int pitchf,
+                      const PoissonCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_mg_prolong<T>, grid2d(nf, nf), dim3(kBlock), 0, st, Ec, nc, pitchc, psi,
+                     nf, pitchf, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_mg_residual(const double* psi, const double* F, double* r, int n, int pitch,
+                              double h, const PoissonCtl* ctl, hipStream_t st) {
+  return mg_residual<double>(psi, F, r, n, pitch, h, ctl, st);
+}
+hipError_t launch_mg_residual(const float* psi, const float* F, float* r, int n, int pitch,
+                              double h, const PoissonCtl* ctl, hipStream_t st) {
+  return mg_residual<float>(psi, F, r, n, pitch, h, ctl, st);
+}
 hipError_t launch_mg_restrict(const double* r, int nf, int pitchf, double* Fc, double* Ec,
                               double* Ecb, int nc, int pitchc, const PoissonCtl* ctl,
                               hipStream_t st) {
-  const double hc = 1.0 / (nc - 1);
-  const double ratio = (double)(nc - 1) / (double)(nf - 1);
-  hipLaunchKernelGGL(k_mg_restrict, grid2d(nc, nc), dim3(kBlock), 0, st, r, nf, pitchf, Fc, Ec,
-                     Ecb, nc, pitchc, 0.3 * hc * hc * ratio * ratio, ctl);
-  return hipGetLastError();
+  return mg_restrict<double>(r, nf, pitchf, Fc, Ec, Ecb, nc, pitchc, ctl, st);
 }
-
+hipError_t launch_mg_restrict(const float* r, int nf, int pitchf, float* Fc, float* Ec,
+                              float* Ecb, int nc, int pitchc, const PoissonCtl* ctl,
+                              hipStream_t st) {
+  return mg_restrict<float>(r, nf, pitchf, Fc, Ec, Ecb, nc, pitchc, ctl, st);
+}
 hipError_t launch_mg_prolong(const double* Ec, int nc, int pitchc, double* psi, int nf, int pitchf,
                              const PoissonCtl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_mg_prolong, grid2d(nf, nf), dim3(kBlock), 0, st, Ec, nc, pitchc, psi, nf,
-                     pitchf, ctl);
-  return hipGetLastError();
+  return mg_prolong<double>(Ec, nc, pitchc, psi, nf, pitchf, ctl, st);
+}
+hipError_t launch_mg_prolong(const float* Ec, int nc, int pitchc, float* psi, int nf, int pitchf,
+                             const PoissonCtl* ctl, hipStream_t st) {
+  return mg_prolong<float>(Ec, nc, pitchc, psi, nf, pitchf, ctl, st);
 }
 
 hipError_t launch_sor64_relax(const SorConfig& cfg, const double* psi_in, double* psi_out,

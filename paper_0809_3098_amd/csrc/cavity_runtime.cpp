@@ -68,6 +68,17 @@ struct MgLevel {
   double* r = nullptr;   // residual in vorticity units (not on the coarsest level)
 };
 
+// FP32 counterpart for the correction cycles of mixed precision (level 0:
+// E = d32a, Eb = d32b, F = R32).
+struct MgLevel32 {
+  int n = 0, pitch = 0;
+  double h = 0;
+  float* E = nullptr;
+  float* Eb = nullptr;
+  float* F = nullptr;
+  float* r = nullptr;
+};
+
 constexpr int kMgCoarsest = 9;     // levels stop at n <= 9
 constexpr int kMgCoarseSweeps = 24;  // relaxation sweeps on the coarsest level
 constexpr double kMgCoarseRelax = 1.5;
@@ -99,6 +110,7 @@ struct Member {
   int inner_sweeps = 0;     // mixed: FP32 sweeps per refinement round
   int solver = CAVITY_SOLVER_SOR;
   std::vector<MgLevel> mg;  // multigrid hierarchy (allocated for every cavity)
+  std::vector<MgLevel32> mg32;  // FP32 hierarchy (mixed cavities)
   // host-side state
   long long step = 0;
   double t = 0;
@@ -245,6 +257,14 @@ size_t mg_bytes(int n) {
   return b;
 }
 
+size_t mg32_bytes(int n) {
+  const std::vector<int> v = mg_sizes(n);
+  size_t b = align_up((size_t)n * pitch_of(n) * sizeof(float));  // level-0 residual
+  for (size_t l = 1; l < v.size(); ++l)
+    b += 4 * align_up((size_t)v[l] * pitch_of(v[l]) * sizeof(float));
+  return b;
+}
+
 size_t member_bytes(const Member& m) {
   const size_t f64 = align_up((size_t)m.n * m.pitch * sizeof(double));
   const size_t f32 = align_up((size_t)m.n * m.pitch * sizeof(float));
@@ -255,6 +275,7 @@ size_t member_bytes(const Member& m) {
   b += align_up((size_t)cav::diag_partials(m.n) * 4 * sizeof(double));
   b += align_up(4 * sizeof(double));
   b += mg_bytes(m.n);
+  if (m.mixed) b += mg32_bytes(m.n);
   return b;
 }
 
@@ -300,6 +321,28 @@ void carve(Member& m, char*& cur) {
       L.Eb = reinterpret_cast<double*>(take(f));
       L.F = reinterpret_cast<double*>(take(f));
       L.r = reinterpret_cast<double*>(take(f));
+    }
+  }
+  m.mg32.clear();
+  if (m.mixed) {
+    m.mg32.assign(v.size(), MgLevel32{});
+    for (size_t l = 0; l < v.size(); ++l) {
+      MgLevel32& L = m.mg32[l];
+      L.n = v[l];
+      L.pitch = pitch_of(v[l]);
+      L.h = 1.0 / (v[l] - 1);
+      const size_t f = align_up((size_t)L.n * L.pitch * sizeof(float));
+      if (l == 0) {
+        L.E = m.d32a;
+        L.Eb = m.d32b;
+        L.F = m.R32;
+        L.r = reinterpret_cast<float*>(take(f));
+      } else {
+        L.E = reinterpret_cast<float*>(take(f));
+        L.Eb = reinterpret_cast<float*>(take(f));
+        L.F = reinterpret_cast<float*>(take(f));
+        L.r = reinterpret_cast<float*>(take(f));
+      }
     }
   }
 }
@@ -377,9 +420,48 @@ int enqueue_vcycle(cavity_s* h, Member& m) {
 // One chunk of work for member m: `units` check groups (FP64: pairs_per_check
 // launch pairs, the last launch checking) or refinement rounds (mixed).
 // Every launch returns at once once the solve has stopped.
+// The same cycle in FP32 for the correction equation of mixed precision:
+// d32a holds the correction, R32 the FP64 residual rounded to FP32.
+int enqueue_vcycle32(cavity_s* h, Member& m) {
+  const int L = (int)m.mg32.size() - 1;
+  for (int l = 0; l < L; ++l) {
+    const MgLevel32& v = m.mg32[l];
+    const MgLevel32& c = m.mg32[l + 1];
+    HIP_TRY(h, cav::launch_sor32(mg_cfg(v.n), v.E, v.Eb, v.F, v.n, v.pitch, m.ctl, 1.0, h->st));
+    HIP_TRY(h, cav::launch_mg_residual(v.Eb, v.F, v.r, v.n, v.pitch, v.h, m.ctl, h->st));
+    HIP_TRY(h, cav::launch_mg_restrict(v.r, v.n, v.pitch, c.F, c.E, c.Eb, c.n, c.pitch, m.ctl,
+                                       h->st));
+  }
+  {
+    const MgLevel32& c = m.mg32[L];
+    const cav::SorConfig cc = mg_cfg(c.n);
+    for (int k = 0; k < kMgCoarseSweeps / (2 * cc.s); ++k) {
+      HIP_TRY(h, cav::launch_sor32(cc, c.E, c.Eb, c.F, c.n, c.pitch, m.ctl, kMgCoarseRelax,
+                                   h->st));
+      HIP_TRY(h, cav::launch_sor32(cc, c.Eb, c.E, c.F, c.n, c.pitch, m.ctl, kMgCoarseRelax,
+                                   h->st));
+    }
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    const MgLevel32& v = m.mg32[l];
+    const MgLevel32& c = m.mg32[l + 1];
+    HIP_TRY(h, cav::launch_mg_prolong(c.E, c.n, c.pitch, v.Eb, v.n, v.pitch, m.ctl, h->st));
+    HIP_TRY(h, cav::launch_sor32(mg_cfg(v.n), v.Eb, v.E, v.F, v.n, v.pitch, m.ctl, 1.0, h->st));
+  }
+  return CAVITY_OK;
+}
+
 int enqueue_chunk(cavity_s* h, Member& m, int units) {
   for (int u = 0; u < units; ++u) {
-    if (m.solver == CAVITY_SOLVER_MG) {
+    if (m.solver == CAVITY_SOLVER_MG && m.mixed) {
+      // FP64 residual (and the decision), one FP32 V-cycle on the
+      // correction, FP64 refinement of psi
+      HIP_TRY(h, cav::launch_resid64(m.psi, m.F, m.R32, m.d32a, m.n, m.pitch, m.ctl, m.part,
+                                     h->st));
+      const int rc = enqueue_vcycle32(h, m);
+      if (rc != CAVITY_OK) return rc;
+      HIP_TRY(h, cav::launch_refine(m.psi, m.d32a, m.n, m.pitch, m.ctl, 2 * kMgNu, h->st));
+    } else if (m.solver == CAVITY_SOLVER_MG) {
       const int rc = enqueue_vcycle(h, m);
       if (rc != CAVITY_OK) return rc;
       HIP_TRY(h, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, m.part,
@@ -414,7 +496,7 @@ int enqueue_chunk(cavity_s* h, Member& m, int units) {
 // Enqueue a residual check without sweeping (FP64): a converged warm start
 // then needs no sweep at all.
 int enqueue_initial_check(cavity_s* h, Member& m) {
-  if (m.mixed) return CAVITY_OK;  // the first refinement round starts with a check
+  if (m.mixed) return CAVITY_OK;  // every refinement round starts with a check
   HIP_TRY(h, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, m.part,
                                  h->st));
   return CAVITY_OK;
@@ -1316,8 +1398,8 @@ int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t) {
   if (t->solver != CAVITY_SOLVER_SOR && t->solver != CAVITY_SOLVER_MG)
     return fail(CAVITY_EINVAL, "unknown solver %d", t->solver);
   Member& m = h->m[idx];
-  if (t->solver == CAVITY_SOLVER_MG && (m.mixed || h->exec != CAVITY_EXEC_STREAM))
-    return fail(CAVITY_EINVAL, "the multigrid solver runs FP64 cavities in stream execution");
+  if (t->solver == CAVITY_SOLVER_MG && h->exec != CAVITY_EXEC_STREAM)
+    return fail(CAVITY_EINVAL, "the multigrid solver runs in stream execution");
   m.solver = t->solver;
   m.cfg64 = c64;
   m.cfg32 = c32;

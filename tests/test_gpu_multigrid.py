@@ -77,3 +77,40 @@ def test_multigrid_step_parity_1024_after_100_steps(cm):
     ew = np.max(np.abs(omega - ref.omega)) / np.max(np.abs(ref.omega))
     print(f"  psi_rel={ep:.3e} omega_rel={ew:.3e} V-cycles/step={st['sweeps_last_step'] // 4}")
     assert ep <= 1e-11 and ew <= 1e-11
+
+
+@pytest.mark.parametrize("n", [64, 257, 1024])
+def test_mixed_multigrid_solve_matches_oracle(cm, n):
+    """FP32 V-cycles on the correction, FP64 residual and refinement: the FP64
+    residual reaches the tolerance, so the same bound holds."""
+    print(f"[mixed mg solve] n={n}", flush=True)
+    omega = inputs.random_field(n, seed=5 * n + 2, scale=0.02)
+    c = _mg(cm, n, precision=cm.CAVITY_MIXED)
+    psi, info = c.poisson(0, omega)
+    c.close()
+    ref = poisson_solve(omega)
+    inv = float(np.max(np.abs(poisson_solve(np.ones((n, n))))))
+    err = np.max(np.abs(psi - ref))
+    bound = 1.02 * inv * info["resid_inf"] + 1e-14 * np.max(np.abs(ref))
+    print(f"  rounds={info['sweeps'] // 4} resid={info['resid_inf']:.3e} err={err:.3e}")
+    assert info["status"] == 0
+    assert err <= bound
+    assert info["sweeps"] // 4 <= 30
+
+
+def test_mixed_multigrid_step_error(cm):
+    n, re, steps = 257, 1.0e4, 40
+    print(f"[mixed mg step] n={n}", flush=True)
+    c = _mg(cm, n, re, precision=cm.CAVITY_MIXED)
+    st = c.step(steps)[0]
+    psi, omega, _, _ = c.fields()
+    c.close()
+    ref = CavityOracle(n, re)
+    d = ref.step(steps, diagnostics_every=steps)
+    ep = np.max(np.abs(psi - ref.psi)) / np.max(np.abs(ref.psi))
+    ew = np.max(np.abs(omega - ref.omega)) / np.max(np.abs(ref.omega))
+    ek = abs(st["ke"] - d["ke"]) / d["ke"]
+    print(f"  psi_rel={ep:.3e} omega_rel={ew:.3e} ke_rel={ek:.3e}")
+    # the FP32 transport stencil bounds these (see test_gpu_mixed); multigrid
+    # changes nothing there
+    assert max(ep, ew, ek) <= 1e-6
