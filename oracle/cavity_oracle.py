@@ -376,11 +376,19 @@ class CavityOracle:
     initial vorticity (default zero); psi is solved from it and the walls are
     then set by Thom's formula, so the stored pair is always consistent.
     ``nu`` overrides the viscosity derived from Re (used for U = 0 tests).
+
+    ``fixed_sweeps`` > 0 selects the coupled reading of eq. (SequationFinal):
+    instead of solving the stream equation, every stage relaxes psi with
+    exactly that many four-colour sweeps of parameter ``beta`` (Sec. 4 gives
+    beta between 0.8 and 0.1), starting from the psi of the stage before it.
+    ``beta`` defaults to 2 / (1 + sin(pi h)).  The initial psi is still the
+    exact solution for ``omega0``.
     """
 
     def __init__(self, n: int, re: float, u_lid: float = 1.0, dt: float | None = None,
                  cfl: float = 0.5, omega0: np.ndarray | None = None,
-                 nu: float | None = None, workers: int | None = None):
+                 nu: float | None = None, workers: int | None = None,
+                 fixed_sweeps: int = 0, beta: float | None = None):
         self.n = int(n)
         self.h = mesh_spacing(self.n)
         self.u_lid = float(u_lid)
@@ -392,6 +400,8 @@ class CavityOracle:
             dt = cfl * self.h / abs(self.u_lid)
         self.dt = float(dt)
         self.workers = workers
+        self.fixed_sweeps = int(fixed_sweeps)
+        self.beta = (2.0 / (1.0 + np.sin(np.pi * self.h))) if beta is None else float(beta)
         w = np.zeros((n, n)) if omega0 is None else np.array(omega0, dtype=np.float64, copy=True)
         self.psi = poisson_solve(w, workers)
         self.omega = thom_walls(w, self.psi, self.h, self.u_lid)
@@ -424,8 +434,14 @@ class CavityOracle:
         w[-1, :] = w_in[-1, :]
         w[:, 0] = w_in[:, 0]
         w[:, -1] = w_in[:, -1]
-        # ... psi is solved for it, then Thom refreshes the walls.
-        psi = poisson_solve(w, self.workers)
+        # ... psi is solved for it (or, in the coupled mode, relaxed from the
+        # input stage's psi), then Thom refreshes the walls.
+        if self.fixed_sweeps > 0:
+            psi = state_in[1]
+            for _ in range(self.fixed_sweeps):
+                psi = sor_four_colour_sweep(psi, w, self.beta)
+        else:
+            psi = poisson_solve(w, self.workers)
         return (thom_walls(w, psi, self.h, self.u_lid), psi)
 
     def step(self, nsteps: int = 1, diagnostics_every: int = 0):
