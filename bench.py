@@ -117,6 +117,13 @@ def main():
                     help="instead of the bench: run the 4096^2 Re 3e4 noise-start cavity "
                          "(mixed, multigrid) for --log-steps steps, one monitor line per step")
     ap.add_argument("--log-steps", type=int, default=2000)
+    ap.add_argument("--grid-study", default=None, metavar="JSONL",
+                    help="instead of the bench: run the coarse-grid cavities of the grid "
+                         "dependence study towards a steady state, one line per chunk")
+    ap.add_argument("--study-steps", type=int, default=200000)
+    ap.add_argument("--study-chunk", type=int, default=5000)
+    ap.add_argument("--study-seconds", type=float, default=240.0,
+                    help="wall-clock limit per cavity of the grid study")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): every workload here is "
@@ -153,6 +160,50 @@ def main():
                     f.flush()
                     print(json.dumps(rec), flush=True)
         cav.close()
+        return
+
+    if args.grid_study:
+        # one handle per cavity, so that a cavity whose run blows up (a possible
+        # outcome on a coarse grid) ends only its own run
+        from paper_0809_3098_amd.cavity import CAVITY_ENONFINITE, CavityError
+        wl = WORKLOADS["grid_dependence"]
+        with open(args.grid_study, "w") as f:
+            for r, m in wl["members"]:
+                cav = Cavity(Params(n=m, re=r, dt=wl["dt"], poisson_tol=wl["tol"]),
+                             device="cuda:0", stream=stream)
+                t0 = time.perf_counter()
+                done, first, outcome = 0, -1, "max_steps"
+                while done < args.study_steps:
+                    chunk = min(args.study_chunk, args.study_steps - done)
+                    try:
+                        steady, stats = cav.run_steady(chunk, 100)
+                    except CavityError as e:
+                        if e.code != CAVITY_ENONFINITE:
+                            raise
+                        outcome = f"non-finite after step {done}"
+                        break
+                    st = stats[0]
+                    done = st["step"]
+                    rec = {"n": m, "re": r, "step": done, "t": round(st["t"], 6),
+                           "wall_s": round(time.perf_counter() - t0, 2),
+                           "res_psi": st["res_psi"], "res_omega": st["res_omega"],
+                           "ke": st["ke"], "domega_inf_over_dt": st["domega_inf_over_dt"],
+                           "sweeps_last_step": st["sweeps_last_step"], "steady_step": steady[0]}
+                    f.write(json.dumps(rec) + "\n")
+                    f.flush()
+                    print(json.dumps(rec), flush=True)
+                    if steady[0] >= 0:
+                        first, outcome = steady[0], "steady"
+                        break
+                    if time.perf_counter() - t0 > args.study_seconds:
+                        outcome = "time limit"
+                        break
+                summary = {"n": m, "re": r, "outcome": outcome, "steady_step": first,
+                           "steps": done, "t": round(done * wl["dt"], 6),
+                           "wall_s": round(time.perf_counter() - t0, 2)}
+                f.write(json.dumps({"summary": summary}) + "\n")
+                print(json.dumps({"summary": summary}), flush=True)
+                cav.close()
         return
 
     def single(name, steps, warmup, mode, solver=0, precision=None):
@@ -213,6 +264,15 @@ def main():
                            CAVITY_SOLVER_MG, CAVITY_FP64)
         c4.close()
         extras["cavity4096_re3e4_noise_fp64_multigrid"] = g4
+        # coupled mode: a fixed 20 sweeps per stage with beta = 0.8 (no stopping test)
+        cc = Cavity(Params(n=n, re=wl["re"], fixed_sweeps=20, sor_omega=0.8), device="cuda:0",
+                    stream=stream)
+        el, st = _timed_steps(torch, cc, args.steps, args.warmup)
+        cc.close()
+        extras["coupled_1024_re1e4_fixed20_beta0.8"] = {
+            "value": round(n * n * args.steps / el / 1e6, 4),
+            "ms_per_step": round(1e3 * el / args.steps, 3),
+            "sweeps_per_stage": st[0]["sweeps_last_step"] / 5, "steps": args.steps}
         # batched six-cavity Reynolds sweep vs one by one
         b = WORKLOADS["re_sweep6"]
         cells = sum(m * m for _, m in b["members"])

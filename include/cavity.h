@@ -86,6 +86,18 @@ typedef struct cavity_params {
                                  Poisson solve (or the saved psi when resume = 1);
                                  its wall values are ignored (psi = 0 on walls);
                                  NULL = zeros                                      */
+  int32_t fixed_sweeps;       /* 0: every stage solves the stream equation to
+                                 poisson_tol.  > 0: coupled mode of Sec. 3 eq.
+                                 (SequationFinal) as a fixed iteration -- every
+                                 stage relaxes psi exactly this many four-colour
+                                 sweeps with parameter sor_omega (the relaxation
+                                 beta; Sec. 4 reports 0.8 down to 0.1 as Re
+                                 grows), starting from the previous stage's psi,
+                                 with no stopping test.  Needs CAVITY_FP64, the
+                                 SOR solver and CAVITY_EXEC_STREAM; the initial
+                                 solve of cavity_create and cavity_poisson still
+                                 solve to poisson_tol                              */
+  int32_t reserved;           /* must be 0                                        */
 } cavity_params;
 
 /* Per-cavity results of cavity_step. */
@@ -149,6 +161,30 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
  * poisoned handle.
  */
 int cavity_step(cavity_t h, int32_t nsteps, cavity_stats* stats);
+
+/*
+ * Advance every cavity until it reaches a steady state in the sense of
+ * Sec. 4: the monitors RES_psi and RES_omega of one step (eqs. resS, resV)
+ * both at or below their thresholds.  The monitors are evaluated on the last
+ * step of every group of check_every steps; the run stops once every cavity
+ * has met its thresholds, or after max_steps steps.  Cavities that met them
+ * keep advancing with the others (a steady state stays steady).
+ *   max_steps      >= 1, steps of this call at most.
+ *   check_every    >= 1, steps between monitor evaluations.
+ *   res_psi_tol, res_omega_tol
+ *                  nullable host arrays[count] of thresholds (> 0); NULL takes
+ *                  the values of Sec. 4: 1e-12 and 1e-10 for Re <= 20 000,
+ *                  1e-10 and 1e-8 above (Re = |u_lid| / nu).
+ *   steady_step    host array[count], out: the step count since create at
+ *                  which the cavity first met its thresholds, -1 if it did
+ *                  not within this call.
+ *   stats          nullable host array[count]: results of the last step.
+ * Synchronises the stream after every group.  Errors as cavity_step; not
+ * reaching a steady state is not an error (steady_step = -1).
+ */
+int cavity_run_steady(cavity_t h, int64_t max_steps, int32_t check_every,
+                      const double* res_psi_tol, const double* res_omega_tol,
+                      int64_t* steady_step, cavity_stats* stats);
 
 /*
  * Solve the compact stream equation for cavity idx.

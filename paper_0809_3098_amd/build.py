@@ -50,7 +50,25 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     _run([cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
+    build_demo(verbose)
     return LIB
+
+
+DEMO_SRC = os.path.join(HERE, "examples", "cavity_step_demo.c")
+DEMO = os.path.join(HERE, "examples", "cavity_step_demo")
+
+
+def build_demo(verbose: bool = False) -> str:
+    """The plain C caller of the ABI, compiled as C99 by the host C compiler."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        raise RuntimeError("no C compiler for the C example")
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    _run([cc, "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__",
+          "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"), DEMO_SRC,
+          "-o", DEMO, "-L", HERE, "-lcavity", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+          "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(rocm, "lib")], verbose)
+    return DEMO
 
 
 def _run(cmd, verbose):

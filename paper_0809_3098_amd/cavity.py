@@ -59,6 +59,7 @@ class cavity_params(ctypes.Structure):
         ("poisson_max_sweeps", ctypes.c_int32), ("resume", ctypes.c_int32),
         ("sor_omega", ctypes.c_double),
         ("omega0", ctypes.c_void_p), ("psi0", ctypes.c_void_p),
+        ("fixed_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -104,6 +105,9 @@ _lib.cavity_workspace_bytes.argtypes = [_P(cavity_params), ctypes.c_int32, _P(ct
 _lib.cavity_create.argtypes = [_P(cavity_params), ctypes.c_int32, ctypes.c_void_p,
                                ctypes.c_size_t, ctypes.c_void_p, _P(ctypes.c_void_p)]
 _lib.cavity_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(cavity_stats)]
+_lib.cavity_run_steady.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                   _P(ctypes.c_double), _P(ctypes.c_double), _P(ctypes.c_int64),
+                                   _P(cavity_stats)]
 _lib.cavity_poisson.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                 ctypes.c_void_p, _P(cavity_poisson_info)]
 _lib.cavity_fields.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
@@ -118,12 +122,14 @@ _lib.cavity_set_exec.argtypes = [ctypes.c_void_p, ctypes.c_int32]
 _lib.cavity_get_exec.argtypes = [ctypes.c_void_p, _P(ctypes.c_int32)]
 _lib.cavity_destroy.argtypes = [ctypes.c_void_p]
 _lib.cavity_last_error.restype = ctypes.c_char_p
-for _f in ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_poisson",
+for _f in ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_run_steady",
+           "cavity_poisson",
            "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
            "cavity_set_exec", "cavity_get_exec", "cavity_autotune", "cavity_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTED = ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_poisson",
+EXPORTED = ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_run_steady",
+            "cavity_poisson",
             "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
             "cavity_set_exec", "cavity_get_exec", "cavity_autotune", "cavity_destroy",
             "cavity_last_error")
@@ -154,13 +160,15 @@ class Params:
     precision: int = CAVITY_FP64
     sor_omega: float = 0.0
     resume: int = 0
+    fixed_sweeps: int = 0
 
     def to_c(self, omega0_ptr: int = 0, psi0_ptr: int = 0) -> cavity_params:
         return cavity_params(n=self.n, precision=self.precision, re=self.re, u_lid=self.u_lid,
                              nu=self.nu, dt=self.dt, cfl=self.cfl, poisson_tol=self.poisson_tol,
                              poisson_max_sweeps=self.poisson_max_sweeps, resume=self.resume,
                              sor_omega=self.sor_omega, omega0=omega0_ptr or None,
-                             psi0=psi0_ptr or None)
+                             psi0=psi0_ptr or None, fixed_sweeps=self.fixed_sweeps,
+                             reserved=0)
 
 
 def _param_array(params: Sequence[cavity_params]):
@@ -194,6 +202,21 @@ def cavity_step(h: int, nsteps: int, count: int = 1, want_stats: bool = True,
     rc = _lib.cavity_step(ctypes.c_void_p(h), nsteps, stats)
     _check(rc, allow=(CAVITY_ENOCONV,) if allow_noconv else ())
     return [s.as_dict() for s in stats] if want_stats else None
+
+
+def cavity_run_steady(h: int, max_steps: int, check_every: int, count: int = 1,
+                      res_psi_tol: Optional[Sequence[float]] = None,
+                      res_omega_tol: Optional[Sequence[float]] = None,
+                      allow_noconv: bool = False):
+    """Returns (steady_step per cavity, stats of the last step per cavity)."""
+    def arr(v):
+        return None if v is None else (ctypes.c_double * count)(*[float(x) for x in v])
+    steady = (ctypes.c_int64 * count)()
+    stats = (cavity_stats * count)()
+    rc = _lib.cavity_run_steady(ctypes.c_void_p(h), max_steps, check_every, arr(res_psi_tol),
+                                arr(res_omega_tol), steady, stats)
+    _check(rc, allow=(CAVITY_ENOCONV,) if allow_noconv else ())
+    return [int(x) for x in steady], [s.as_dict() for s in stats]
 
 
 def cavity_poisson(h: int, idx: int, omega_ptr: int = 0, psi_ptr: int = 0,
@@ -301,6 +324,11 @@ class Cavity:
 
     def step(self, nsteps: int = 1, want_stats: bool = True, allow_noconv: bool = False):
         return cavity_step(self.handle, nsteps, self.count, want_stats, allow_noconv)
+
+    def run_steady(self, max_steps: int, check_every: int = 10, res_psi_tol=None,
+                   res_omega_tol=None, allow_noconv: bool = False):
+        return cavity_run_steady(self.handle, max_steps, check_every, self.count, res_psi_tol,
+                                 res_omega_tol, allow_noconv)
 
     def poisson(self, idx: int = 0, omega=None, want_psi: bool = True, allow_noconv=False):
         torch = self._torch

@@ -172,14 +172,19 @@ __device__ void check_and_decide(PoissonCtl* ctl, double* part, double rmax, dou
 // classes (i mod 2, j mod 2) visited (0,0), (1,0), (0,1), (1,1); no two nodes
 // of a class share a nine-point stencil.
 //
-// A block loads an output tile plus a halo of H = 4S + 2 nodes of psi and F
-// into LDS, runs S sweeps (4S colour passes) there, and writes the tile.  A
-// node's value after colour pass k is exact when every node within
-// Chebyshev distance k of it was loaded, so pass k only updates nodes at
-// least k from the region edge, and after 4S passes the tile and its first
-// ring are exact: the tile's residual can be evaluated in LDS as well.
-// LDS holds each field as four parity planes, so all reads of a colour pass
-// are unit-stride across lanes.
+// A block loads an output tile plus a halo of H = 4S + 2 nodes of psi into
+// LDS, runs S sweeps (4S colour passes) there, and writes the tile.  A node's
+// value after colour pass k is exact when every node within Chebyshev
+// distance k of it was loaded, so pass k only updates nodes at least k from
+// the region edge, and after 4S passes the tile and its first ring are exact:
+// the tile's residual can be evaluated in LDS as well.  LDS holds psi as four
+// parity planes, so all reads of a colour pass are unit-stride across lanes.
+//
+// Each thread owns one column (lane) of a strip of K rows in every plane; the
+// values of its own nodes and their right-hand sides F live in registers, so
+// a colour pass reads only neighbours from LDS: the east and the upper
+// diagonal neighbour are loaded, the west ones come from the lane to the left
+// by a DPP wavefront shift, and walking up the strip reuses the row below.
 // ---------------------------------------------------------------------------
 template <typename T, int TX, int TY, int S>
 struct SorGeom {
@@ -190,9 +195,29 @@ struct SorGeom {
   static constexpr int RXH = RX / 2;
   static constexpr int RYH = RY / 2;
   static constexpr int PLANE = RXH * RYH;
-  static constexpr size_t LDS = 2ull * 4ull * PLANE * sizeof(T);
+  // four parity planes, then one row of 64 slots that takes the stores of
+  // lanes beyond a plane row
+  static constexpr int SINK = 4 * PLANE;
+  static constexpr size_t LDS = (4ull * PLANE + 64) * sizeof(T);
   static_assert(LDS <= 163840, "tile does not fit in 160 KiB of LDS");
+  static_assert(RXH <= 64, "a plane row must fit one wavefront");
 };
+
+// Value held by the lane one to the left (DPP wave_shr:1; lane 0 receives 0)
+// or one to the right (wave_shl:1; lane 63 receives 0).
+template <int CTRL>
+__device__ inline double lane_shift(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ inline float lane_shift(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppShr1 = 0x138;  // from lane - 1
+constexpr int kDppShl1 = 0x130;  // from lane + 1
 
 template <typename T>
 __device__ inline T fma_t(T a, T b, T c) { return fma(a, b, c); }
@@ -203,119 +228,198 @@ template <typename T> struct Pair;
 template <> struct Pair<double> { using type = double2; };
 template <> struct Pair<float> { using type = float2; };
 
+// One colour pass C (parity class (C & 1, C >> 1)) of pass number k over the
+// nodes this thread owns.
+template <typename T, int TX, int TY, int S, int NT, int C>
+__device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][(SorGeom<T, TX, TY, S>::RYH + NT / 64 - 1) / (NT / 64)],
+                                            const T (&fv)[4][(SorGeom<T, TX, TY, S>::RYH + NT / 64 - 1) / (NT / 64)],
+                                            int k, int lxd0, int lxd1, int lyd0, int lyd1,
+                                            int lane, int b0, T w) {
+  using G = SorGeom<T, TX, TY, S>;
+  constexpr int K = (G::RYH + NT / 64 - 1) / (NT / 64);
+  constexpr int cx = C & 1, cy = C >> 1;
+  const int lxlo = max(k, lxd0), lxhi = min(G::RX - 1 - k, lxd1);
+  const int lylo = max(k, lyd0), lyhi = min(G::RY - 1 - k, lyd1);
+  const int a0 = (lxlo - cx + 1) >> 1, a1 = (lxhi - cx) >> 1;
+  const int bmin = (lylo - cy + 1) >> 1, bmax = (lyhi - cy) >> 1;
+  T* own = sp + C * G::PLANE;
+  const T* ew = sp + (cy * 2 + (1 - cx)) * G::PLANE;
+  const T* ns = sp + ((1 - cy) * 2 + cx) * G::PLANE;
+  const T* dg = sp + ((1 - cy) * 2 + (1 - cx)) * G::PLANE;
+  const bool lane_ok = lane >= a0 && lane <= a1;
+  // Lane l holds column l of every plane.  A node of x parity cx = 0 (at
+  // 2l) has its east neighbours in column l of the odd-x planes and its west
+  // ones in column l - 1, the left lane's; for cx = 1 (at 2l + 1) the west
+  // ones are in column l and the east ones in the right lane's column l + 1.
+  // Only region-edge nodes lack that lane (cx = 0: lane 0, x = 0; cx = 1: the
+  // last column, x = RX - 1), and no pass updates them, so every neighbour is
+  // one LDS read of the lane's own column plus one DPP shift.
+  const int ic = min(lane, G::RXH - 1);
+  constexpr int kOther = cx == 0 ? kDppShr1 : kDppShl1;
+  const T c4 = T(0.2), cd = T(0.05);
+  T sN_prev = T(0), dN_prev = T(0), dNo_prev = T(0);
+  bool have = false;
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    const int b = b0 + r;
+    if (b < bmin || b > bmax) {  // uniform across the wavefront
+      have = false;
+      continue;
+    }
+    const int rn = (b + cy) * G::RXH;  // row of N, NE, NW
+    const int rs = rn - G::RXH;        // row of S, SE, SW
+    T sS, dS, dSo;
+    if (have) {
+      sS = sN_prev;
+      dS = dN_prev;
+      dSo = dNo_prev;
+    } else {
+      sS = ns[rs + ic];
+      dS = dg[rs + ic];
+      dSo = lane_shift<kOther>(dS);
+    }
+    const T sN = ns[rn + ic];
+    const T dN = dg[rn + ic];
+    const T dNo = lane_shift<kOther>(dN);
+    const T e = ew[b * G::RXH + ic];
+    const T eo = lane_shift<kOther>(e);
+    // Every lane computes; lanes outside the pass keep their value (held in
+    // pv, equal to the plane's) and store it back unchanged, so the pass has
+    // no divergent branch.  Lanes beyond the row store to the sink.
+    const T s4 = (e + eo) + (sN + sS);
+    const T sd = (dN + dNo) + (dS + dSo);
+    const T p = pv[C][r];
+    const T g = fma_t(c4, s4, fma_t(cd, sd, fv[C][r]));
+    const T np = lane_ok ? fma_t(w, g - p, p) : p;
+    pv[C][r] = np;
+    own[lane < G::RXH ? b * G::RXH + lane : G::SINK - C * G::PLANE + lane] = np;
+    sN_prev = sN;
+    dN_prev = dN;
+    dNo_prev = dNo;
+    have = true;
+  }
+  __syncthreads();
+}
+
 // One tile of S sweeps, shared by the per-launch kernel and the persistent
-// batched kernel.  sp / sf are the block's LDS planes.  With CHECK the
-// block-wide maxima of |g - psi| and |psi| over the tile are returned in
-// thread 0's rmax / pmax.
+// batched kernel.  sp is the block's LDS (four parity planes of psi).  With
+// CHECK the block-wide maxima of |g - psi| and |psi| over the tile are
+// returned in thread 0's rmax / pmax.
 template <typename T, int TX, int TY, int S, int NT, bool CHECK>
 __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restrict__ pout,
                                          const T* __restrict__ F, int n, int pitch, int tile,
-                                         int tiles_x, T w, T* sp, T* sf, double& rmax_out,
+                                         int tiles_x, T w, T* sp, double& rmax_out,
                                          double& pmax_out) {
   using G = SorGeom<T, TX, TY, S>;
   using T2 = typename Pair<T>::type;
+  constexpr int K = (G::RYH + NT / 64 - 1) / (NT / 64);
   const int tyi = tile / tiles_x;
   const int txi = tile - tyi * tiles_x;
   const int x0 = txi * TX - G::H;  // region origin, even
   const int y0 = tyi * TY - G::H;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  // the wavefront index is uniform: keeping it in a scalar register makes the
+  // per-row range tests of the colour passes scalar branches
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int b0 = wave * K;         // first owned row of every plane
 
-  // Region load in pairs of nodes (x even, x odd), coalesced along x.  All
-  // global loads of a thread are issued before its LDS stores.
+  // Region load of psi in pairs of nodes (x even, x odd), coalesced along x;
+  // all global loads of a thread are issued before its LDS stores.
   constexpr int RXP = G::RX / 2;
   constexpr int NPAIR = RXP * G::RY;
   constexpr int NL = (NPAIR + NT - 1) / NT;
-  T2 lv[NL], lf[NL];
+  T2 lv[NL];
 #pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const int idx = tid + k * NT;
-    lv[k].x = lv[k].y = T(0);
-    lf[k].x = lf[k].y = T(0);
+  for (int q = 0; q < NL; ++q) {
+    const int idx = tid + q * NT;
+    lv[q].x = lv[q].y = T(0);
     if (idx < NPAIR) {
       const int ly = idx / RXP;
       const int gx = x0 + 2 * (idx - ly * RXP), gy = y0 + ly;
       if ((unsigned)gy < (unsigned)n && gx >= 0) {
         const size_t g = (size_t)gy * pitch + gx;
         if (gx + 1 < n) {
-          lv[k] = *reinterpret_cast<const T2*>(pin + g);
-          lf[k] = *reinterpret_cast<const T2*>(F + g);
+          lv[q] = *reinterpret_cast<const T2*>(pin + g);
         } else if (gx < n) {
-          lv[k].x = pin[g];
-          lf[k].x = F[g];
+          lv[q].x = pin[g];
         }
       }
     }
   }
+  // Right-hand side of the owned nodes, straight into registers.
+  T fv[4][K];
 #pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const int idx = tid + k * NT;
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const int gx = x0 + 2 * lane + (c & 1), gy = y0 + 2 * (b0 + r) + (c >> 1);
+      const bool in = lane < G::RXH && b0 + r < G::RYH && (unsigned)gx < (unsigned)n &&
+                      (unsigned)gy < (unsigned)n;
+      fv[c][r] = in ? F[(size_t)gy * pitch + gx] : T(0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int idx = tid + q * NT;
     if (idx < NPAIR) {
       const int ly = idx / RXP;
       const int o = ((ly & 1) << 1) * G::PLANE + (ly >> 1) * G::RXH + (idx - ly * RXP);
-      sp[o] = lv[k].x;
-      sp[o + G::PLANE] = lv[k].y;
-      sf[o] = lf[k].x;
-      sf[o + G::PLANE] = lf[k].y;
+      sp[o] = lv[q].x;
+      sp[o + G::PLANE] = lv[q].y;
     }
   }
   __syncthreads();
+  T pv[4][K];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const bool in = lane < G::RXH && b0 + r < G::RYH;
+      pv[c][r] = in ? sp[c * G::PLANE + (b0 + r) * G::RXH + lane] : T(0);
+    }
+  }
 
   const int lxd0 = 1 - x0, lxd1 = n - 2 - x0;  // domain interior in local coordinates
   const int lyd0 = 1 - y0, lyd1 = n - 2 - y0;
-  const int lane = tid & 63, wave = tid >> 6;
-  const T c4 = T(0.2), cd = T(0.05);
-
 #pragma unroll 1
-  for (int k = 1; k <= 4 * S; ++k) {
-    const int c = (k - 1) & 3;
-    const int cx = c & 1, cy = c >> 1;
-    const int lxlo = max(k, lxd0), lxhi = min(G::RX - 1 - k, lxd1);
-    const int lylo = max(k, lyd0), lyhi = min(G::RY - 1 - k, lyd1);
-    const int a0 = (lxlo - cx + 1) >> 1, a1 = (lxhi - cx) >> 1;
-    const int b0 = (lylo - cy + 1) >> 1, b1 = (lyhi - cy) >> 1;
-    T* own = sp + (cy * 2 + cx) * G::PLANE;
-    const T* ew = sp + (cy * 2 + (1 - cx)) * G::PLANE;
-    const T* ns = sp + ((1 - cy) * 2 + cx) * G::PLANE;
-    const T* dg = sp + ((1 - cy) * 2 + (1 - cx)) * G::PLANE;
-    const T* ff = sf + (cy * 2 + cx) * G::PLANE;
-    for (int bb = b0 + wave; bb <= b1; bb += NT / 64) {
-      for (int aa = a0 + lane; aa <= a1; aa += 64) {
-        const int o = bb * G::RXH + aa;
-        const int oE = o + cx;                 // E at oE, W at oE - 1
-        const int oN = o + cy * G::RXH;        // N at oN, S at oN - RXH
-        const int oNE = oN + cx;               // NE, NW = oNE - 1, SE, SW one row down
-        const T s4 = (ew[oE] + ew[oE - 1]) + (ns[oN] + ns[oN - G::RXH]);
-        const T sd = (dg[oNE] + dg[oNE - 1]) + (dg[oNE - G::RXH] + dg[oNE - G::RXH - 1]);
-        const T p = own[o];
-        const T g = fma_t(c4, s4, fma_t(cd, sd, ff[o]));
-        own[o] = fma_t(w, g - p, p);
-      }
-    }
-    __syncthreads();
+  for (int s = 0; s < S; ++s) {
+    const int k = 4 * s;
+    colour_pass<T, TX, TY, S, NT, 0>(sp, pv, fv, k + 1, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    colour_pass<T, TX, TY, S, NT, 1>(sp, pv, fv, k + 2, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    colour_pass<T, TX, TY, S, NT, 2>(sp, pv, fv, k + 3, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    colour_pass<T, TX, TY, S, NT, 3>(sp, pv, fv, k + 4, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
   }
 
-  // Write the tile; with CHECK also its residual max |g - psi| and max |psi|.
+  // Write the owned tile nodes; with CHECK also the tile's residual
+  // max |g - psi| and max |psi|.
+  const T c4 = T(0.2), cd = T(0.05);
   double rmax = 0.0, pmax = 0.0;
-  for (int idx = tid; idx < TX * TY; idx += NT) {
-    const int ty = idx / TX;
-    const int lx = G::H + (idx - ty * TX);
-    const int ly = G::H + ty;
-    const int gx = x0 + lx, gy = y0 + ly;
-    if (gx < 1 || gx > n - 2 || gy < 1 || gy > n - 2) continue;
-    const int cx = lx & 1, cy = ly & 1;
-    const int o = (ly >> 1) * G::RXH + (lx >> 1);
-    const T p = sp[(cy * 2 + cx) * G::PLANE + o];
-    pout[(size_t)gy * pitch + gx] = p;
-    if (CHECK) {
-      const T* ew = sp + (cy * 2 + (1 - cx)) * G::PLANE;
-      const T* ns = sp + ((1 - cy) * 2 + cx) * G::PLANE;
-      const T* dg = sp + ((1 - cy) * 2 + (1 - cx)) * G::PLANE;
-      const int oE = o + cx, oN = o + cy * G::RXH, oNE = oN + cx;
-      const T s4 = (ew[oE] + ew[oE - 1]) + (ns[oN] + ns[oN - G::RXH]);
-      const T sd = (dg[oNE] + dg[oNE - 1]) + (dg[oNE - G::RXH] + dg[oNE - G::RXH - 1]);
-      const T g = fma_t(c4, s4, fma_t(cd, sd, sf[(cy * 2 + cx) * G::PLANE + o]));
-      rmax = fmax(rmax, mag((double)(g - p)));
-      pmax = fmax(pmax, mag((double)p));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int cx = c & 1, cy = c >> 1;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const int b = b0 + r;
+      const int lx = 2 * lane + cx, ly = 2 * b + cy;
+      if (lane >= G::RXH || b >= G::RYH) continue;
+      if (lx < G::H || lx >= G::H + TX || ly < G::H || ly >= G::H + TY) continue;
+      const int gx = x0 + lx, gy = y0 + ly;
+      if (gx < 1 || gx > n - 2 || gy < 1 || gy > n - 2) continue;
+      const T p = pv[c][r];
+      pout[(size_t)gy * pitch + gx] = p;
+      if (CHECK) {
+        const T* ew = sp + (cy * 2 + (1 - cx)) * G::PLANE;
+        const T* ns = sp + ((1 - cy) * 2 + cx) * G::PLANE;
+        const T* dg = sp + ((1 - cy) * 2 + (1 - cx)) * G::PLANE;
+        const int o = b * G::RXH + lane;
+        const int oE = o + cx, oN = o + cy * G::RXH, oNE = oN + cx;
+        const T s4 = (ew[oE] + ew[oE - 1]) + (ns[oN] + ns[oN - G::RXH]);
+        const T sd = (dg[oNE] + dg[oNE - 1]) + (dg[oNE - G::RXH] + dg[oNE - G::RXH - 1]);
+        const T g = fma_t(c4, s4, fma_t(cd, sd, fv[c][r]));
+        rmax = fmax(rmax, mag((double)(g - p)));
+        pmax = fmax(pmax, mag((double)p));
+      }
     }
   }
   if (CHECK) block_max2<NT>(rmax, pmax);
@@ -329,15 +433,14 @@ __global__ __launch_bounds__(NT) void k_sor(const T* __restrict__ pin, T* __rest
                                             PoissonCtl* __restrict__ ctl, double* __restrict__ part,
                                             int tiles_x, int xcd_bands, double relax_arg) {
   using G = SorGeom<T, TX, TY, S>;
-  __shared__ T sp[4 * G::PLANE];
-  __shared__ T sf[4 * G::PLANE];
+  __shared__ T sp[G::SINK + 64];
   if (ctl->state != SOLVE_RUN) return;
   const T w = (T)(relax_arg > 0.0 ? relax_arg : ctl->relax);
   const int nb = gridDim.x;
   int tile = blockIdx.x;
   if (xcd_bands && (nb & 7) == 0) tile = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
   double rmax = 0.0, pmax = 0.0;
-  sor_tile<T, TX, TY, S, NT, CHECK>(pin, pout, F, n, pitch, tile, tiles_x, w, sp, sf, rmax, pmax);
+  sor_tile<T, TX, TY, S, NT, CHECK>(pin, pout, F, n, pitch, tile, tiles_x, w, sp, rmax, pmax);
   if (CHECK) check_and_decide_reduced<NT>(ctl, part, rmax, pmax, -1);
 }
 
@@ -467,8 +570,7 @@ __global__ __launch_bounds__(NT) void k_batch64(const BatchMember* __restrict__ 
                                                 unsigned int* __restrict__ flags,
                                                 long long spin_ticks) {
   using G = SorGeom<double, TX, TY, S>;
-  __shared__ double sp[4 * G::PLANE];
-  __shared__ double sf[4 * G::PLANE];
+  __shared__ double sp[G::SINK + 64];
   const unsigned int nb = gridDim.x;
   unsigned int gen = batch_epoch(bc);
   while (any_running(mem, count)) {
@@ -485,14 +587,14 @@ __global__ __launch_bounds__(NT) void k_batch64(const BatchMember* __restrict__ 
         double rmax = 0.0, pmax = 0.0;
         if (check) {
           sor_tile<double, TX, TY, S, NT, true>(pin, pout, m.F, m.n, m.pitch, lt, m.tiles_x, w,
-                                                sp, sf, rmax, pmax);
+                                                sp, rmax, pmax);
           if (threadIdx.x == 0) {
             m.part[2 * lt] = rmax;
             m.part[2 * lt + 1] = pmax;
           }
         } else {
           sor_tile<double, TX, TY, S, NT, false>(pin, pout, m.F, m.n, m.pitch, lt, m.tiles_x, w,
-                                                 sp, sf, rmax, pmax);
+                                                 sp, rmax, pmax);
         }
         __syncthreads();
       }
@@ -511,8 +613,7 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
                                                     unsigned int* __restrict__ flags,
                                                     long long spin_ticks) {
   using G = SorGeom<float, TX, TY, S>;
-  __shared__ float sp[4 * G::PLANE];
-  __shared__ float sf[4 * G::PLANE];
+  __shared__ float sp[G::SINK + 64];
   const unsigned int nb = gridDim.x;
   unsigned int gen = batch_epoch(bc);
   for (;;) {
@@ -561,7 +662,7 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
         double rm = 0.0, pm = 0.0;
         sor_tile<float, TX, TY, S, NT, false>(fwd ? m.d32a : m.d32b, fwd ? m.d32b : m.d32a,
                                               m.R32, m.n, m.pitch, t - m.tile0, m.tiles_x, w,
-                                              sp, sf, rm, pm);
+                                              sp, rm, pm);
         __syncthreads();
       }
       if (!grid_sync(bc, flags, nb, gen, spin_ticks)) return;
@@ -1028,12 +1129,13 @@ hipError_t sor_launch(const T* pin, T* pout, const T* F, int n, int pitch, Poiss
   X(32, 32, 2, 256)            \
   X(64, 32, 2, 512)            \
   X(64, 64, 1, 1024)           \
-  X(64, 64, 2, 256)            \
   X(64, 64, 2, 1024)           \
   X(64, 64, 3, 1024)           \
+  X(64, 64, 2, 512)            \
+  X(64, 64, 4, 512)            \
   X(64, 64, 4, 1024)           \
-  X(128, 32, 2, 1024)          \
-  X(96, 64, 2, 1024)
+  X(96, 64, 2, 1024)           \
+  X(96, 64, 3, 1024)
 
 #define CAV_SOR_CONFIGS_F32(X) \
   X(32, 32, 1, 256)            \
@@ -1042,8 +1144,8 @@ hipError_t sor_launch(const T* pin, T* pout, const T* F, int n, int pitch, Poiss
   X(64, 64, 2, 512)            \
   X(64, 64, 2, 1024)           \
   X(64, 64, 4, 1024)           \
-  X(128, 64, 3, 1024)          \
-  X(128, 64, 4, 1024)          \
+  X(64, 64, 6, 1024)           \
+  X(96, 64, 3, 1024)           \
   X(96, 96, 3, 1024)
 
 template <typename T>
@@ -1136,17 +1238,15 @@ int sor_max_blocks(int n) { return ((n + 31) / 32) * ((n + 31) / 32); }
 #define CAV_BATCH_CONFIGS_F64(X) \
   X(32, 32, 1, 256)              \
   X(64, 32, 2, 512)              \
-  X(64, 64, 1, 1024)             \
-  X(64, 64, 2, 1024)             \
-  X(64, 64, 3, 1024)             \
-  X(64, 64, 4, 1024)
+  X(64, 64, 2, 512)              \
+  X(64, 64, 4, 512)
 
 #define CAV_BATCH_CONFIGS_F32(X) \
   X(32, 32, 1, 256)              \
   X(64, 32, 2, 512)              \
   X(64, 64, 2, 1024)             \
   X(64, 64, 4, 1024)             \
-  X(128, 64, 4, 1024)
+  X(96, 64, 3, 1024)
 
 bool batch_config_supported(const SorConfig& c, bool mixed) {
   if (c.xcd_bands != 0) return false;

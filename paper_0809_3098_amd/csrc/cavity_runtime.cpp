@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -109,6 +110,7 @@ struct Member {
   int pairs_per_check = 1;  // FP64: launch pairs between residual checks
   int inner_sweeps = 0;     // mixed: FP32 sweeps per refinement round
   int solver = CAVITY_SOLVER_SOR;
+  int fixed = 0;            // > 0: sweeps per stage solve of the coupled mode
   std::vector<MgLevel> mg;  // multigrid hierarchy (allocated for every cavity)
   std::vector<MgLevel32> mg32;  // FP32 hierarchy (mixed cavities)
   // host-side state
@@ -134,7 +136,7 @@ struct cavity_s {
   // ---- execution of the Poisson solves
   int exec = CAVITY_EXEC_STREAM;
   bool mixed = false;                   // batch precision (all members agree)
-  cav::SorConfig bcfg64{64, 64, 4, 1024, 0};
+  cav::SorConfig bcfg64{64, 64, 2, 512, 0};
   cav::SorConfig bcfg32{64, 64, 4, 1024, 0};
   int b_ppc = 1;                        // FP64: launch-pairs per check
   int b_inner_pairs = 1;                // mixed: FP32 launch-pairs per round
@@ -182,6 +184,11 @@ int derive(const cavity_params& p, Member& m) {
     return fail(CAVITY_EINVAL, "resume = 1 needs both omega0 and psi0");
   if (p.precision != CAVITY_FP64 && p.precision != CAVITY_MIXED)
     return fail(CAVITY_EINVAL, "precision = %d is not CAVITY_FP64 or CAVITY_MIXED", p.precision);
+  if (p.reserved != 0) return fail(CAVITY_EINVAL, "reserved must be 0");
+  if (p.fixed_sweeps < 0 || p.fixed_sweeps > (1 << 24))
+    return fail(CAVITY_EINVAL, "fixed_sweeps = %d outside [0, 2^24]", p.fixed_sweeps);
+  if (p.fixed_sweeps > 0 && p.precision != CAVITY_FP64)
+    return fail(CAVITY_EINVAL, "fixed_sweeps needs precision CAVITY_FP64");
   const double vals[] = {p.re, p.u_lid, p.nu, p.dt, p.cfl, p.poisson_tol, p.sor_omega};
   for (double v : vals)
     if (!std::isfinite(v)) return fail(CAVITY_EINVAL, "non-finite parameter");
@@ -204,6 +211,7 @@ int derive(const cavity_params& p, Member& m) {
     const double cfl = p.cfl > 0 ? p.cfl : 0.5;
     m.dt = cfl * m.h / std::fabs(p.u_lid);
   }
+  m.fixed = p.fixed_sweeps;
   m.tol = p.poisson_tol > 0 ? p.poisson_tol : 1e-10;
   m.max_sweeps = p.poisson_max_sweeps > 0 ? p.poisson_max_sweeps : 200LL * p.n;
   if (p.sor_omega > 0) {
@@ -583,6 +591,62 @@ int solve_members(cavity_s* h, const std::vector<int>& idx, bool state_solve = t
   return worst;
 }
 
+// Coupled mode (fixed_sweeps > 0): exactly m.fixed four-colour sweeps with
+// relaxation m.relax from the psi left by the previous stage, no stopping
+// test.  The last launch still evaluates the residual, against a tolerance of
+// the largest double, so its check always ends the solve: the residual is
+// reported and a non-finite one is counted in the control block's totals.
+// Sweeps per launch do not change the result (every node sees the same
+// neighbour values in the same colour order), so a remainder is swept with a
+// one-sweep kernel.
+int enqueue_fixed(cavity_s* h, Member& m) {
+  HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, DBL_MAX, m.fixed, m.fixed, m.fixed, h->st));
+  const cav::SorConfig one{32, 32, 1, 256, 0};
+  const int full = m.fixed / m.cfg64.s, rem = m.fixed % m.cfg64.s;
+  const int launches = full + rem;
+  double* a = m.psi;
+  double* b = m.psi_b;
+  for (int j = 0; j < launches; ++j) {
+    const int check = (j == launches - 1) ? 1 : 0;
+    HIP_TRY(h, cav::launch_sor64(j < full ? m.cfg64 : one, a, b, m.F, m.n, m.pitch, m.ctl,
+                                 m.part, check, h->st));
+    std::swap(a, b);
+  }
+  if (a != m.psi) HIP_TRY(h, cav::launch_copy(a, m.psi, m.n, m.pitch, h->st));
+  return CAVITY_OK;
+}
+
+// After a step of coupled-mode members: sweeps, last residual and the
+// non-finite check, from the control blocks' running totals (the step may
+// have been a graph replay, with no host code between its launches).
+int finish_fixed(cavity_s* h, const std::vector<int>& idx) {
+  if (idx.empty()) return CAVITY_OK;
+  const int rc = read_ctls(h, idx);
+  if (rc != CAVITY_OK) return rc;
+  for (int k : idx) {
+    Member& m = h->m[k];
+    const cav::PoissonCtl& c = h->host_ctl[k];
+    cav::PoissonCtl& l = h->last_tot[k];
+    const long long d = c.total_sweeps - l.total_sweeps;
+    m.sweeps_step += d;
+    m.sweeps_total += d;
+    m.last_resid = c.last * (10.0 / 3.0) / (m.h * m.h);
+    const bool nonfinite = c.total_nonfinite > l.total_nonfinite;
+    l = c;
+    if (nonfinite) {
+      h->poisoned = true;
+      return fail(CAVITY_ENONFINITE, "non-finite Poisson residual in cavity %d", k);
+    }
+  }
+  return CAVITY_OK;
+}
+
+bool all_fixed(const cavity_s* h) {
+  for (const Member& m : h->m)
+    if (m.fixed == 0) return false;
+  return true;
+}
+
 int enqueue_rhs_and_walls_prep(cavity_s* h, Member& m, const double* omega) {
   HIP_TRY(h, cav::launch_poisson_rhs(omega, m.F, m.n, m.pitch, m.h, h->st));
   return CAVITY_OK;
@@ -765,6 +829,18 @@ int enqueue_thom(cavity_s* h, int stage) {
   return CAVITY_OK;
 }
 
+// The whole step of coupled-mode cavities as pure enqueues.
+int enqueue_step_fixed(cavity_s* h) {
+  int rc;
+  for (int stage = 1; stage <= 5; ++stage) {
+    if ((rc = enqueue_stage(h, stage)) != CAVITY_OK) return rc;
+    for (Member& m : h->m)
+      if ((rc = enqueue_fixed(h, m)) != CAVITY_OK) return rc;
+    if ((rc = enqueue_thom(h, stage)) != CAVITY_OK) return rc;
+  }
+  return CAVITY_OK;
+}
+
 // The whole step as pure enqueues (persistent solves): what a graph captures.
 int enqueue_step_persistent(cavity_s* h) {
   int rc;
@@ -785,7 +861,7 @@ int launch_step_graph(cavity_s* h) {
     HIP_TRY(h, hipStreamBeginCapture(h->cap_st, hipStreamCaptureModeThreadLocal));
     hipStream_t user = h->st;
     h->st = h->cap_st;
-    const int rc = enqueue_step_persistent(h);
+    const int rc = all_fixed(h) ? enqueue_step_fixed(h) : enqueue_step_persistent(h);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(h->cap_st, &g);
     h->st = user;
@@ -811,15 +887,23 @@ int step_all(cavity_s* h, bool want_diag) {
     if (want_diag) HIP_TRY(h, cav::launch_copy(m.psi, m.psi_prev, m.n, m.pitch, h->st));
   }
   if (h->exec == CAVITY_EXEC_STREAM) {
-    std::vector<int> all(h->count);
-    for (int k = 0; k < h->count; ++k) all[k] = k;
+    std::vector<int> solved, fixed;
+    for (int k = 0; k < h->count; ++k) (h->m[k].fixed > 0 ? fixed : solved).push_back(k);
     for (int stage = 1; stage <= 5; ++stage) {
       if ((rc = enqueue_stage(h, stage)) != CAVITY_OK) return rc;
-      rc = solve_members(h, all);
+      for (int k : fixed)
+        if ((rc = enqueue_fixed(h, h->m[k])) != CAVITY_OK) return rc;
+      rc = solved.empty() ? CAVITY_OK : solve_members(h, solved);
       if (rc == CAVITY_ENONFINITE || rc == CAVITY_EHIP) return rc;
       if (rc != CAVITY_OK) worst = rc;
       if ((rc = enqueue_thom(h, stage)) != CAVITY_OK) return rc;
     }
+    if ((rc = finish_fixed(h, fixed)) != CAVITY_OK) return rc;
+  } else if (all_fixed(h)) {
+    if ((rc = launch_step_graph(h)) != CAVITY_OK) return rc;
+    std::vector<int> all(h->count);
+    for (int k = 0; k < h->count; ++k) all[k] = k;
+    if ((rc = finish_fixed(h, all)) != CAVITY_OK) return rc;
   } else {
     rc = (h->exec == CAVITY_EXEC_GRAPH) ? launch_step_graph(h) : enqueue_step_persistent(h);
     if (rc != CAVITY_OK) return rc;
@@ -1032,6 +1116,40 @@ void cache_store(const char* path, const std::string& key, const cavity_tuning& 
   fclose(f);
 }
 
+// Copy every member's monitors of the last logged step to the host.
+int read_diag(cavity_s* h) {
+  for (int k = 0; k < h->count; ++k)
+    HIP_TRY(h, hipMemcpyAsync(&h->host_diag[4 * k], h->m[k].diag_out, 4 * sizeof(double),
+                              hipMemcpyDeviceToHost, h->st));
+  HIP_TRY(h, hipStreamSynchronize(h->st));
+  return CAVITY_OK;
+}
+
+// Per-member results; the monitors (Sec. 3.2, eqs. resS and resV) come from
+// the last read_diag when have_diag.
+void fill_stats(const cavity_s* h, bool have_diag, cavity_stats* stats) {
+  for (int k = 0; k < h->count; ++k) {
+    const Member& m = h->m[k];
+    cavity_stats& o = stats[k];
+    std::memset(&o, 0, sizeof o);
+    o.step = m.step;
+    o.t = m.t;
+    o.dt = m.dt;
+    if (have_diag) {
+      const double* d = &h->host_diag[4 * k];
+      o.res_psi = d[0] / m.n;
+      o.res_omega = d[1] / m.n;
+      o.domega_inf_over_dt = d[2] / m.dt;
+      o.ke = 0.5 * m.h * m.h * d[3];
+    }
+    o.last_resid_inf = m.last_resid;
+    o.sweeps_total = m.sweeps_total;
+    o.sweeps_last_step = m.sweeps_step;
+    o.floor_limited = m.floor_step;
+    o.status = m.status_step;
+  }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1165,14 +1283,16 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
     int inner = 0;
     for (const Member& m : h->m) inner = std::max(inner, m.inner_sweeps);
     const int small = h->m[0].n <= 320 && count == 1;
-    h->bcfg64 = small ? cav::SorConfig{32, 32, 1, 256, 0} : cav::SorConfig{64, 64, 4, 1024, 0};
+    h->bcfg64 = small ? cav::SorConfig{32, 32, 1, 256, 0} : cav::SorConfig{64, 64, 2, 512, 0};
     h->bcfg32 = small ? cav::SorConfig{32, 32, 1, 256, 0} : cav::SorConfig{64, 64, 4, 1024, 0};
     h->b_ppc = std::max(1, 32 / (2 * h->bcfg64.s));
     h->b_inner_pairs = std::max(1, (inner + 2 * h->bcfg32.s - 1) / (2 * h->bcfg32.s));
   }
   const int rc2 = collect_totals(h, false);
   if (rc2 != CAVITY_OK) return bail(rc2);
-  if (count > 1 && uniform) {
+  bool any_fixed = false;
+  for (const Member& m : h->m) any_fixed = any_fixed || m.fixed > 0;
+  if (count > 1 && uniform && !any_fixed) {
     const int rc3 = setup_batch(h);
     if (rc3 != CAVITY_OK) return bail(rc3);
     h->exec = CAVITY_EXEC_GRAPH;
@@ -1194,34 +1314,57 @@ int cavity_step(cavity_t h, int32_t nsteps, cavity_stats* stats) {
     if (rc != CAVITY_OK) worst = rc;
   }
   if (stats) {
-    for (int k = 0; k < h->count; ++k) {
-      Member& m = h->m[k];
-      if (nsteps > 0)
-        HIP_TRY(h, hipMemcpyAsync(&h->host_diag[4 * k], m.diag_out, 4 * sizeof(double),
-                                  hipMemcpyDeviceToHost, h->st));
+    if (nsteps > 0) {
+      const int rc = read_diag(h);
+      if (rc != CAVITY_OK) return rc;
     }
-    HIP_TRY(h, hipStreamSynchronize(h->st));
+    fill_stats(h, nsteps > 0, stats);
+  }
+  return worst;
+}
+
+int cavity_run_steady(cavity_t h, int64_t max_steps, int32_t check_every,
+                      const double* res_psi_tol, const double* res_omega_tol,
+                      int64_t* steady_step, cavity_stats* stats) {
+  if (!h) return fail(CAVITY_EINVAL, "null handle");
+  if (h->poisoned) return fail(CAVITY_ESTATE, "handle poisoned by an earlier failure");
+  if (max_steps < 1 || check_every < 1)
+    return fail(CAVITY_EINVAL, "max_steps and check_every must be >= 1");
+  if (!steady_step) return fail(CAVITY_EINVAL, "steady_step must not be NULL");
+  std::vector<double> tp(h->count), tw(h->count);
+  for (int k = 0; k < h->count; ++k) {
+    const Member& m = h->m[k];
+    // Sec. 4: 1e-12 / 1e-10 up to Re = 20 000, 1e-10 / 1e-8 above
+    const double re = std::fabs(m.u_lid) / m.nu;
+    tp[k] = res_psi_tol ? res_psi_tol[k] : (re <= 20000.0 ? 1e-12 : 1e-10);
+    tw[k] = res_omega_tol ? res_omega_tol[k] : (re <= 20000.0 ? 1e-10 : 1e-8);
+    if (!(tp[k] > 0) || !(tw[k] > 0) || !std::isfinite(tp[k]) || !std::isfinite(tw[k]))
+      return fail(CAVITY_EINVAL, "thresholds of cavity %d must be finite and > 0", k);
+    steady_step[k] = -1;
+  }
+  HIP_TRY(h, hipSetDevice(h->device));
+  int worst = CAVITY_OK, pending = h->count;
+  long long done = 0;
+  while (done < max_steps && pending > 0) {
+    const long long chunk = std::min<long long>(check_every, max_steps - done);
+    for (long long s = 0; s < chunk; ++s) {
+      const int rc = step_all(h, s == chunk - 1);
+      if (rc == CAVITY_ENONFINITE || rc == CAVITY_EHIP) return rc;
+      if (rc != CAVITY_OK) worst = rc;
+    }
+    done += chunk;
+    const int rc = read_diag(h);
+    if (rc != CAVITY_OK) return rc;
     for (int k = 0; k < h->count; ++k) {
-      Member& m = h->m[k];
-      cavity_stats& o = stats[k];
-      std::memset(&o, 0, sizeof o);
-      o.step = m.step;
-      o.t = m.t;
-      o.dt = m.dt;
-      if (nsteps > 0) {
-        const double* d = &h->host_diag[4 * k];
-        o.res_psi = d[0] / m.n;
-        o.res_omega = d[1] / m.n;
-        o.domega_inf_over_dt = d[2] / m.dt;
-        o.ke = 0.5 * m.h * m.h * d[3];
+      const Member& m = h->m[k];
+      const double* d = &h->host_diag[4 * k];
+      if (steady_step[k] < 0 && d[0] / m.n <= tp[k] && d[1] / m.n <= tw[k]) {
+        steady_step[k] = m.step;
+        --pending;
       }
-      o.last_resid_inf = m.last_resid;
-      o.sweeps_total = m.sweeps_total;
-      o.sweeps_last_step = m.sweeps_step;
-      o.floor_limited = m.floor_step;
-      o.status = m.status_step;
     }
   }
+  if (stats) fill_stats(h, true, stats);
   return worst;
 }
 
@@ -1255,6 +1398,9 @@ int cavity_poisson(cavity_t h, int32_t idx, const double* d_omega, double* d_psi
   if (!d_omega)
     HIP_TRY(h, cav::launch_thom(m.psi, m.w[0], m.n, m.pitch, m.h, m.u_lid, h->st));
   if (d_psi) HIP_TRY(h, cav::launch_copy_out(result, d_psi, m.n, m.pitch, h->st));
+  // the solve's counts are not a step's: batched and coupled steps count
+  // from these totals
+  if (h->last_tot.size() == (size_t)h->count) h->last_tot[idx] = h->host_ctl[idx];
   if (info) {
     HIP_TRY(h, hipStreamSynchronize(h->st));
     const cav::PoissonCtl& c = h->host_ctl[idx];
@@ -1400,12 +1546,15 @@ int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t) {
   Member& m = h->m[idx];
   if (t->solver == CAVITY_SOLVER_MG && h->exec != CAVITY_EXEC_STREAM)
     return fail(CAVITY_EINVAL, "the multigrid solver runs in stream execution");
+  if (t->solver == CAVITY_SOLVER_MG && m.fixed > 0)
+    return fail(CAVITY_EINVAL, "fixed_sweeps runs the SOR solver only");
   m.solver = t->solver;
   m.cfg64 = c64;
   m.cfg32 = c32;
   m.relax = t->sor_omega;
   set_schedule(m, t->check_every, t->inner_sweeps);
   m.est_sweeps = 0;
+  destroy_graphs(h);  // captured launches carry the old configuration and relaxation
   return CAVITY_OK;
 }
 
@@ -1424,12 +1573,14 @@ int cavity_autotune(cavity_t h, int32_t idx, const char* cache_path, cavity_tuni
   }
   if ((rc = cavity_get_tuning(h, idx, &t)) != CAVITY_OK) return rc;
   struct Cand { int tx, ty, s, nt, xcd; };
-  static const Cand k64[] = {{32, 32, 1, 256, 0}, {32, 32, 2, 256, 0}, {64, 32, 2, 512, 0},
+  static const std::vector<Cand> k64 = {{32, 32, 1, 256, 0}, {32, 32, 2, 256, 0}, {64, 32, 2, 512, 0},
                              {64, 64, 1, 1024, 0}, {64, 64, 2, 1024, 0}, {64, 64, 3, 1024, 0},
-                             {64, 64, 4, 1024, 0}, {128, 32, 2, 1024, 0}, {96, 64, 2, 1024, 0}};
-  static const Cand k32[] = {{32, 32, 1, 256, 0}, {32, 32, 2, 256, 0}, {64, 32, 2, 512, 0},
+                             {64, 64, 2, 512, 0},  {64, 64, 4, 512, 0},  {64, 64, 4, 1024, 0},
+                             {96, 64, 2, 1024, 0},
+                             {96, 64, 3, 1024, 0}};
+  static const std::vector<Cand> k32 = {{32, 32, 1, 256, 0}, {32, 32, 2, 256, 0}, {64, 32, 2, 512, 0},
                              {64, 64, 2, 512, 0}, {64, 64, 2, 1024, 0}, {64, 64, 4, 1024, 0},
-                             {128, 64, 3, 1024, 0}, {128, 64, 4, 1024, 0}, {96, 96, 3, 1024, 0}};
+                             {64, 64, 6, 1024, 0}, {96, 64, 3, 1024, 0}, {96, 96, 3, 1024, 0}};
   if (idx >= 0) {
     Member& m = h->m[idx];
     // 1. tile shape, sweeps per launch and tile order, by sweep time
@@ -1532,12 +1683,20 @@ int cavity_set_exec(cavity_t h, int32_t mode) {
   if (mode != CAVITY_EXEC_STREAM && mode != CAVITY_EXEC_PERSISTENT && mode != CAVITY_EXEC_GRAPH)
     return fail(CAVITY_EINVAL, "unknown execution mode %d", mode);
   HIP_TRY(h, hipSetDevice(h->device));
-  if (mode != CAVITY_EXEC_STREAM) {
+  if (mode == CAVITY_EXEC_GRAPH && all_fixed(h)) {
+    // coupled mode: the step has no decision to wait for, the graph holds
+    // the per-launch kernels as they are
+    const int rc = collect_totals(h, false);
+    if (rc != CAVITY_OK) return rc;
+  } else if (mode != CAVITY_EXEC_STREAM) {
     for (const Member& m : h->m) {
       if (m.mixed != h->mixed)
         return fail(CAVITY_EINVAL, "batched execution needs one precision for all cavities");
       if (m.solver != CAVITY_SOLVER_SOR)
         return fail(CAVITY_EINVAL, "batched execution runs the SOR solver only");
+      if (m.fixed > 0)
+        return fail(CAVITY_EINVAL, "fixed_sweeps runs in stream or graph execution, with every "
+                                   "cavity of the handle in the coupled mode for graphs");
     }
     int rc = setup_batch(h);
     if (rc != CAVITY_OK) return rc;

@@ -45,10 +45,37 @@ def test_library_exports_every_declared_symbol(binding):
 
 def test_struct_layout_matches_header(binding):
     # offsets of the C structs as laid out by a C compiler for this header
-    assert ctypes.sizeof(binding.cavity_params) == 88
+    assert ctypes.sizeof(binding.cavity_params) == 96
     assert binding.cavity_params.omega0.offset == 72
+    assert binding.cavity_params.fixed_sweeps.offset == 88
     assert ctypes.sizeof(binding.cavity_stats) == 88
     assert ctypes.sizeof(binding.cavity_poisson_info) == 24
+
+
+def test_struct_layout_matches_c_compiler(binding, tmp_path):
+    """ctypes layouts against offsetof/sizeof from gcc on the header itself."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    checks = []
+    for sname in ("cavity_params", "cavity_stats", "cavity_poisson_info", "cavity_tuning"):
+        cls = getattr(binding, sname)
+        checks.append((f"sizeof({sname})", ctypes.sizeof(cls)))
+        for fname, _ in cls._fields_:
+            checks.append((f"offsetof({sname}, {fname})", getattr(cls, fname).offset))
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("%zu\\n", (size_t){e});\n' for e, _ in checks)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "cavity.h"\n'
+                   f"int main(void) {{\n{body}  return 0;\n}}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    for (expr, want), g in zip(checks, got):
+        assert g == want, expr
 
 
 def test_workspace_bytes_scales_with_grid(binding):
@@ -73,6 +100,8 @@ def test_workspace_bytes_scales_with_grid(binding):
     (dict(n=64, sor_omega=2.0), "sor_omega"),
     (dict(n=64, precision=7), "precision"),
     (dict(n=64, resume=1), "resume"),
+    (dict(n=64, fixed_sweeps=-1), "fixed_sweeps"),
+    (dict(n=64, fixed_sweeps=4, precision=1), "fixed_sweeps needs"),
 ])
 def test_invalid_parameters_are_rejected(binding, kw, msg):
     with pytest.raises(binding.CavityError) as e:

@@ -41,7 +41,7 @@ def test_batch_bitwise_equals_solo_runs(cm, mode, precision):
     print(f"[batch {mode} precision={precision}] {members}", flush=True)
     c = cm.Cavity([cm.Params(n=n, re=re, precision=precision) for re, n in members])
     c.set_exec(cm.CAVITY_EXEC_PERSISTENT if mode == "persistent" else cm.CAVITY_EXEC_GRAPH)
-    c.set_tuning(-1, tile_x=64, tile_y=64, sweeps_per_launch=s, threads=1024,
+    c.set_tuning(-1, tile_x=64, tile_y=64, sweeps_per_launch=s, threads=512,
                  tile_x32=64, tile_y32=64, sweeps_per_launch32=s, threads32=1024,
                  check_every=check_every, inner_sweeps=inner)
     solos = [_solo(cm, n, re, precision, s, check_every, inner) for re, n in members]
