@@ -110,8 +110,11 @@ def main():
     ap.add_argument("--exec", default="stream", choices=sorted(EXEC))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed and batched lines")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--relax-launches", type=int, default=200)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a cold 1 GiB device copy (torch), the known-size kernel the "
+                         "HBM counters of a profiling run are scaled by")
     ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--log-run", default=None, metavar="JSONL",
                     help="instead of the bench: run the 4096^2 Re 3e4 noise-start cavity "
@@ -309,6 +312,16 @@ def main():
         "extras": extras,
     }
     print(json.dumps(line), flush=True)
+    if args.copy_calibration:
+        # 1 GiB source, then 1 GiB of other writes so that the source has left
+        # the caches, then one copy: its counters should read 1 GiB each way
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        evict = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(2.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize(dev)
+        dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        del src, evict, dst
 
 
 if __name__ == "__main__":

@@ -278,10 +278,14 @@ int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t);
  *                           decisions on the device); one readback per step.
  *   CAVITY_EXEC_GRAPH       as PERSISTENT, with the whole step (five stages)
  *                           captured once per buffer parity in a hipGraph and
- *                           replayed (default for count > 1).
- * Both persistent modes need one precision for all cavities (EINVAL
- * otherwise).  With the same tile sweeps per launch, check spacing and
- * relaxation, all three modes give bitwise identical results.
+ *                           replayed (default for count > 1).  When every
+ *                           cavity is in the coupled mode (fixed_sweeps > 0)
+ *                           the graph holds the per-launch sweeps instead.
+ * Both persistent modes need one precision for all cavities and the SOR
+ * solver; a coupled cavity allows STREAM, and GRAPH only if all cavities of
+ * the handle are coupled (EINVAL otherwise).  With the same tile sweeps per
+ * launch, check spacing and relaxation, all three modes give bitwise
+ * identical results.
  */
 enum cavity_exec { CAVITY_EXEC_STREAM = 0, CAVITY_EXEC_PERSISTENT = 1, CAVITY_EXEC_GRAPH = 2 };
 int cavity_set_exec(cavity_t h, int32_t mode);

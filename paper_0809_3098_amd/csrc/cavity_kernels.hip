@@ -182,39 +182,47 @@ __device__ void check_and_decide(PoissonCtl* ctl, double* part, double rmax, dou
 //
 // Each thread owns one column (lane) of a strip of K rows in every plane; the
 // values of its own nodes and their right-hand sides F live in registers, so
-// a colour pass reads only neighbours from LDS: the east and the upper
-// diagonal neighbour are loaded, the west ones come from the lane to the left
-// by a DPP wavefront shift, and walking up the strip reuses the row below.
+// a colour pass reads only neighbours from LDS: one read of the lane's own
+// column per neighbour row, the other-side column from the adjacent lane by
+// a DPP wavefront shift, and walking up the strip reuses the row below.
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TY, int S>
+template <typename T, int TX, int TY, int S, int NT>
 struct SorGeom {
   static_assert(TX % 2 == 0 && TY % 2 == 0, "tile sizes must be even");
+  static_assert(NT % 64 == 0, "whole wavefronts");
   static constexpr int H = 4 * S + 2;
   static constexpr int RX = TX + 2 * H;
   static constexpr int RY = TY + 2 * H;
   static constexpr int RXH = RX / 2;
   static constexpr int RYH = RY / 2;
   static constexpr int PLANE = RXH * RYH;
-  // four parity planes, then one row of 64 slots that takes the stores of
-  // lanes beyond a plane row
-  static constexpr int SINK = 4 * PLANE;
-  static constexpr size_t LDS = (4ull * PLANE + 64) * sizeof(T);
+  static constexpr int NW = NT / 64;               // wavefronts
+  static constexpr int K = (RYH + NW - 1) / NW;    // plane rows per wavefront
+  // LDS: one pad row, the four parity planes, then enough rows that a strip
+  // may read one row below its first and one above its last row without a
+  // bounds test (those values are never used), and at least 64 slots that
+  // take the stores of lanes beyond a plane row.
+  static constexpr int BASE = RXH;
+  static constexpr int TAIL_ROWS = (NW * K + 1 - RYH) > 0 ? (NW * K + 1 - RYH) : 0;
+  static constexpr int SINK = BASE + 4 * PLANE;
+  static constexpr int TAIL = TAIL_ROWS * RXH > 64 ? TAIL_ROWS * RXH : 64;
+  static constexpr int SLOTS = SINK + TAIL;
+  static constexpr size_t LDS = (size_t)SLOTS * sizeof(T);
   static_assert(LDS <= 163840, "tile does not fit in 160 KiB of LDS");
   static_assert(RXH <= 64, "a plane row must fit one wavefront");
 };
 
-// Value held by the lane one to the left (DPP wave_shr:1; lane 0 receives 0)
-// or one to the right (wave_shl:1; lane 63 receives 0).
+// Value held by the lane one to the left (DPP wave_shr:1) or one to the right
+// (wave_shl:1); the lane without a source receives 0.
 template <int CTRL>
 __device__ inline double lane_shift(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 template <int CTRL>
 __device__ inline float lane_shift(float v) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 constexpr int kDppShr1 = 0x138;  // from lane - 1
 constexpr int kDppShl1 = 0x130;  // from lane + 1
@@ -229,24 +237,25 @@ template <> struct Pair<double> { using type = double2; };
 template <> struct Pair<float> { using type = float2; };
 
 // One colour pass C (parity class (C & 1, C >> 1)) of pass number k over the
-// nodes this thread owns.
+// nodes this thread owns.  sp points at the first plane.
 template <typename T, int TX, int TY, int S, int NT, int C>
-__device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][(SorGeom<T, TX, TY, S>::RYH + NT / 64 - 1) / (NT / 64)],
-                                            const T (&fv)[4][(SorGeom<T, TX, TY, S>::RYH + NT / 64 - 1) / (NT / 64)],
+__device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][SorGeom<T, TX, TY, S, NT>::K],
+                                            const T (&fv)[4][SorGeom<T, TX, TY, S, NT>::K],
                                             int k, int lxd0, int lxd1, int lyd0, int lyd1,
                                             int lane, int b0, T w) {
-  using G = SorGeom<T, TX, TY, S>;
-  constexpr int K = (G::RYH + NT / 64 - 1) / (NT / 64);
+  using G = SorGeom<T, TX, TY, S, NT>;
+  constexpr int K = G::K;
   constexpr int cx = C & 1, cy = C >> 1;
   const int lxlo = max(k, lxd0), lxhi = min(G::RX - 1 - k, lxd1);
   const int lylo = max(k, lyd0), lyhi = min(G::RY - 1 - k, lyd1);
   const int a0 = (lxlo - cx + 1) >> 1, a1 = (lxhi - cx) >> 1;
-  const int bmin = (lylo - cy + 1) >> 1, bmax = (lyhi - cy) >> 1;
+  // the strip's rows inside the pass (wave-uniform)
+  const int r_lo = max((lylo - cy + 1) >> 1, b0) - b0;
+  const int r_hi = min((lyhi - cy) >> 1, b0 + K - 1) - b0;
   T* own = sp + C * G::PLANE;
   const T* ew = sp + (cy * 2 + (1 - cx)) * G::PLANE;
   const T* ns = sp + ((1 - cy) * 2 + cx) * G::PLANE;
   const T* dg = sp + ((1 - cy) * 2 + (1 - cx)) * G::PLANE;
-  const bool lane_ok = lane >= a0 && lane <= a1;
   // Lane l holds column l of every plane.  A node of x parity cx = 0 (at
   // 2l) has its east neighbours in column l of the odd-x planes and its west
   // ones in column l - 1, the left lane's; for cx = 1 (at 2l + 1) the west
@@ -256,63 +265,114 @@ __device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][(SorGeom<T, TX, TY
   // one LDS read of the lane's own column plus one DPP shift.
   const int ic = min(lane, G::RXH - 1);
   constexpr int kOther = cx == 0 ? kDppShr1 : kDppShl1;
+  // Lanes outside the pass relax with 0: they keep their value (held in pv,
+  // equal to the plane's) and store it back, so the pass has no divergent
+  // branch; lanes beyond a plane row store to the sink.
+  const T wl = (lane >= a0 && lane <= a1) ? w : T(0);
+  const int wr = lane < G::RXH ? b0 * G::RXH + lane : G::SINK - G::BASE - C * G::PLANE + lane;
+  const int wstep = lane < G::RXH ? G::RXH : 0;
   const T c4 = T(0.2), cd = T(0.05);
-  T sN_prev = T(0), dN_prev = T(0), dNo_prev = T(0);
-  bool have = false;
+  if (r_lo <= r_hi) {
+    // The south row of the strip's first row; every later row takes the
+    // north values of the row below it.  Rows outside the pass are read too
+    // (the padding keeps them inside LDS), so the chain has no selects.
+    const int rs0 = (b0 + cy - 1) * G::RXH + ic;
+    T sS = ns[rs0];
+    T dS = dg[rs0];
+    T dSo = lane_shift<kOther>(dS);
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const int b = b0 + r;
+      const int rn = (b + cy) * G::RXH + ic;
+      const T sN = ns[rn];
+      const T dN = dg[rn];
+      const T dNo = lane_shift<kOther>(dN);
+      if (r >= r_lo && r <= r_hi) {  // wave-uniform
+        const T e = ew[b * G::RXH + ic];
+        const T eo = lane_shift<kOther>(e);
+        const T s4 = (e + eo) + (sN + sS);
+        const T sd = (dN + dNo) + (dS + dSo);
+        const T p = pv[C][r];
+        const T g = fma_t(c4, s4, fma_t(cd, sd, fv[C][r]));
+        const T np = fma_t(wl, g - p, p);
+        pv[C][r] = np;
+        own[wr + r * wstep] = np;
+      }
+      sS = sN;
+      dS = dN;
+      dSo = dNo;
+    }
+  }
+  __syncthreads();
+}
+
+// Residual of colour C over the tile's own interior nodes after the sweeps:
+// max |g - psi| and max |psi| accumulated into rmax / pmax.  Same neighbour
+// reads and the same arithmetic as the update, no stores.
+template <typename T, int TX, int TY, int S, int NT, int C>
+__device__ __forceinline__ void residual_pass(const T* pl,
+                                              const T (&pv)[4][SorGeom<T, TX, TY, S, NT>::K],
+                                              const T (&fv)[4][SorGeom<T, TX, TY, S, NT>::K],
+                                              int lxd0, int lxd1, int lyd0, int lyd1, int lane,
+                                              int b0, double& rmax, double& pmax) {
+  using G = SorGeom<T, TX, TY, S, NT>;
+  constexpr int K = G::K;
+  constexpr int cx = C & 1, cy = C >> 1;
+  const int lxlo = max(G::H, lxd0), lxhi = min(G::H + TX - 1, lxd1);
+  const int lylo = max(G::H, lyd0), lyhi = min(G::H + TY - 1, lyd1);
+  const int a0 = (lxlo - cx + 1) >> 1, a1 = (lxhi - cx) >> 1;
+  const int r_lo = max((lylo - cy + 1) >> 1, b0) - b0;
+  const int r_hi = min((lyhi - cy) >> 1, b0 + K - 1) - b0;
+  if (r_lo > r_hi) return;
+  const T* ew = pl + (cy * 2 + (1 - cx)) * G::PLANE;
+  const T* ns = pl + ((1 - cy) * 2 + cx) * G::PLANE;
+  const T* dg = pl + ((1 - cy) * 2 + (1 - cx)) * G::PLANE;
+  const int ic = min(lane, G::RXH - 1);
+  constexpr int kOther = cx == 0 ? kDppShr1 : kDppShl1;
+  const bool lane_in = lane >= a0 && lane <= a1;
+  const T c4 = T(0.2), cd = T(0.05);
+  const int rs0 = (b0 + cy - 1) * G::RXH + ic;
+  T sS = ns[rs0];
+  T dS = dg[rs0];
+  T dSo = lane_shift<kOther>(dS);
 #pragma unroll
   for (int r = 0; r < K; ++r) {
     const int b = b0 + r;
-    if (b < bmin || b > bmax) {  // uniform across the wavefront
-      have = false;
-      continue;
-    }
-    const int rn = (b + cy) * G::RXH;  // row of N, NE, NW
-    const int rs = rn - G::RXH;        // row of S, SE, SW
-    T sS, dS, dSo;
-    if (have) {
-      sS = sN_prev;
-      dS = dN_prev;
-      dSo = dNo_prev;
-    } else {
-      sS = ns[rs + ic];
-      dS = dg[rs + ic];
-      dSo = lane_shift<kOther>(dS);
-    }
-    const T sN = ns[rn + ic];
-    const T dN = dg[rn + ic];
+    const int rn = (b + cy) * G::RXH + ic;
+    const T sN = ns[rn];
+    const T dN = dg[rn];
     const T dNo = lane_shift<kOther>(dN);
-    const T e = ew[b * G::RXH + ic];
-    const T eo = lane_shift<kOther>(e);
-    // Every lane computes; lanes outside the pass keep their value (held in
-    // pv, equal to the plane's) and store it back unchanged, so the pass has
-    // no divergent branch.  Lanes beyond the row store to the sink.
-    const T s4 = (e + eo) + (sN + sS);
-    const T sd = (dN + dNo) + (dS + dSo);
-    const T p = pv[C][r];
-    const T g = fma_t(c4, s4, fma_t(cd, sd, fv[C][r]));
-    const T np = lane_ok ? fma_t(w, g - p, p) : p;
-    pv[C][r] = np;
-    own[lane < G::RXH ? b * G::RXH + lane : G::SINK - C * G::PLANE + lane] = np;
-    sN_prev = sN;
-    dN_prev = dN;
-    dNo_prev = dNo;
-    have = true;
+    if (r >= r_lo && r <= r_hi) {  // wave-uniform
+      const T e = ew[b * G::RXH + ic];
+      const T eo = lane_shift<kOther>(e);
+      const T s4 = (e + eo) + (sN + sS);
+      const T sd = (dN + dNo) + (dS + dSo);
+      const T p = pv[C][r];
+      const T g = fma_t(c4, s4, fma_t(cd, sd, fv[C][r]));
+      if (lane_in) {
+        rmax = fmax(rmax, mag((double)(g - p)));
+        pmax = fmax(pmax, mag((double)p));
+      }
+    }
+    sS = sN;
+    dS = dN;
+    dSo = dNo;
   }
-  __syncthreads();
 }
 
 // One tile of S sweeps, shared by the per-launch kernel and the persistent
 // batched kernel.  sp is the block's LDS (four parity planes of psi).  With
 // CHECK the block-wide maxima of |g - psi| and |psi| over the tile are
 // returned in thread 0's rmax / pmax.
-template <typename T, int TX, int TY, int S, int NT, bool CHECK>
+template <typename T, int TX, int TY, int S, int NT>
 __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restrict__ pout,
                                          const T* __restrict__ F, int n, int pitch, int tile,
-                                         int tiles_x, T w, T* sp, double& rmax_out,
+                                         int tiles_x, T w, T* sp, bool CHECK, double& rmax_out,
                                          double& pmax_out) {
-  using G = SorGeom<T, TX, TY, S>;
+  using G = SorGeom<T, TX, TY, S, NT>;
   using T2 = typename Pair<T>::type;
-  constexpr int K = (G::RYH + NT / 64 - 1) / (NT / 64);
+  constexpr int K = G::K;
+  T* const pl = sp + G::BASE;  // first parity plane
   const int tyi = tile / tiles_x;
   const int txi = tile - tyi * tiles_x;
   const int x0 = txi * TX - G::H;  // region origin, even
@@ -347,16 +407,27 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
       }
     }
   }
-  // Right-hand side of the owned nodes, straight into registers.
+  // Right-hand side of the owned nodes, straight into registers: the nodes
+  // of x parity 0 and 1 at one lane and row are neighbours in memory, so one
+  // pair load serves colours (0, cy) and (1, cy).
   T fv[4][K];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int cy = 0; cy < 2; ++cy) {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-      const int gx = x0 + 2 * lane + (c & 1), gy = y0 + 2 * (b0 + r) + (c >> 1);
-      const bool in = lane < G::RXH && b0 + r < G::RYH && (unsigned)gx < (unsigned)n &&
-                      (unsigned)gy < (unsigned)n;
-      fv[c][r] = in ? F[(size_t)gy * pitch + gx] : T(0);
+      const int gx = x0 + 2 * lane, gy = y0 + 2 * (b0 + r) + cy;
+      T2 f;
+      f.x = f.y = T(0);
+      if (lane < G::RXH && b0 + r < G::RYH && (unsigned)gy < (unsigned)n && gx >= 0) {
+        const size_t g = (size_t)gy * pitch + gx;
+        if (gx + 1 < n) {
+          f = *reinterpret_cast<const T2*>(F + g);
+        } else if (gx < n) {
+          f.x = F[g];
+        }
+      }
+      fv[2 * cy][r] = f.x;
+      fv[2 * cy + 1][r] = f.y;
     }
   }
 #pragma unroll
@@ -365,8 +436,8 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
     if (idx < NPAIR) {
       const int ly = idx / RXP;
       const int o = ((ly & 1) << 1) * G::PLANE + (ly >> 1) * G::RXH + (idx - ly * RXP);
-      sp[o] = lv[q].x;
-      sp[o + G::PLANE] = lv[q].y;
+      pl[o] = lv[q].x;
+      pl[o + G::PLANE] = lv[q].y;
     }
   }
   __syncthreads();
@@ -376,7 +447,7 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
 #pragma unroll
     for (int r = 0; r < K; ++r) {
       const bool in = lane < G::RXH && b0 + r < G::RYH;
-      pv[c][r] = in ? sp[c * G::PLANE + (b0 + r) * G::RXH + lane] : T(0);
+      pv[c][r] = in ? pl[c * G::PLANE + (b0 + r) * G::RXH + lane] : T(0);
     }
   }
 
@@ -385,42 +456,47 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
 #pragma unroll 1
   for (int s = 0; s < S; ++s) {
     const int k = 4 * s;
-    colour_pass<T, TX, TY, S, NT, 0>(sp, pv, fv, k + 1, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
-    colour_pass<T, TX, TY, S, NT, 1>(sp, pv, fv, k + 2, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
-    colour_pass<T, TX, TY, S, NT, 2>(sp, pv, fv, k + 3, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
-    colour_pass<T, TX, TY, S, NT, 3>(sp, pv, fv, k + 4, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    colour_pass<T, TX, TY, S, NT, 0>(pl, pv, fv, k + 1, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    colour_pass<T, TX, TY, S, NT, 1>(pl, pv, fv, k + 2, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    colour_pass<T, TX, TY, S, NT, 2>(pl, pv, fv, k + 3, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    colour_pass<T, TX, TY, S, NT, 3>(pl, pv, fv, k + 4, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
   }
 
-  // Write the owned tile nodes; with CHECK also the tile's residual
-  // max |g - psi| and max |psi|.
-  const T c4 = T(0.2), cd = T(0.05);
+  // Write the owned tile nodes, a pair (x even, x odd) per store where both
+  // are interior nodes; with CHECK also the tile's residual max |g - psi| and
+  // max |psi|.
   double rmax = 0.0, pmax = 0.0;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int cx = c & 1, cy = c >> 1;
+  for (int cy = 0; cy < 2; ++cy) {
 #pragma unroll
     for (int r = 0; r < K; ++r) {
       const int b = b0 + r;
-      const int lx = 2 * lane + cx, ly = 2 * b + cy;
+      const int lx = 2 * lane, ly = 2 * b + cy;
+      // both nodes of the pair are in the tile or neither (H and TX even)
       if (lane >= G::RXH || b >= G::RYH) continue;
       if (lx < G::H || lx >= G::H + TX || ly < G::H || ly >= G::H + TY) continue;
       const int gx = x0 + lx, gy = y0 + ly;
-      if (gx < 1 || gx > n - 2 || gy < 1 || gy > n - 2) continue;
-      const T p = pv[c][r];
-      pout[(size_t)gy * pitch + gx] = p;
-      if (CHECK) {
-        const T* ew = sp + (cy * 2 + (1 - cx)) * G::PLANE;
-        const T* ns = sp + ((1 - cy) * 2 + cx) * G::PLANE;
-        const T* dg = sp + ((1 - cy) * 2 + (1 - cx)) * G::PLANE;
-        const int o = b * G::RXH + lane;
-        const int oE = o + cx, oN = o + cy * G::RXH, oNE = oN + cx;
-        const T s4 = (ew[oE] + ew[oE - 1]) + (ns[oN] + ns[oN - G::RXH]);
-        const T sd = (dg[oNE] + dg[oNE - 1]) + (dg[oNE - G::RXH] + dg[oNE - G::RXH - 1]);
-        const T g = fma_t(c4, s4, fma_t(cd, sd, fv[c][r]));
-        rmax = fmax(rmax, mag((double)(g - p)));
-        pmax = fmax(pmax, mag((double)p));
+      if (gy < 1 || gy > n - 2) continue;
+      const bool in0 = gx >= 1 && gx <= n - 2;
+      const bool in1 = gx + 1 <= n - 2;  // gx + 1 >= 1 always
+      const size_t g = (size_t)gy * pitch + gx;
+      if (in0 && in1) {
+        T2 v;
+        v.x = pv[2 * cy][r];
+        v.y = pv[2 * cy + 1][r];
+        *reinterpret_cast<T2*>(pout + g) = v;
+      } else if (in0) {
+        pout[g] = pv[2 * cy][r];
+      } else if (in1) {
+        pout[g + 1] = pv[2 * cy + 1][r];
       }
     }
+  }
+  if (CHECK) {
+    residual_pass<T, TX, TY, S, NT, 0>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
+    residual_pass<T, TX, TY, S, NT, 1>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
+    residual_pass<T, TX, TY, S, NT, 2>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
+    residual_pass<T, TX, TY, S, NT, 3>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
   }
   if (CHECK) block_max2<NT>(rmax, pmax);
   rmax_out = rmax;
@@ -432,15 +508,15 @@ __global__ __launch_bounds__(NT) void k_sor(const T* __restrict__ pin, T* __rest
                                             const T* __restrict__ F, int n, int pitch,
                                             PoissonCtl* __restrict__ ctl, double* __restrict__ part,
                                             int tiles_x, int xcd_bands, double relax_arg) {
-  using G = SorGeom<T, TX, TY, S>;
-  __shared__ T sp[G::SINK + 64];
+  using G = SorGeom<T, TX, TY, S, NT>;
+  __shared__ T sp[G::SLOTS];
   if (ctl->state != SOLVE_RUN) return;
   const T w = (T)(relax_arg > 0.0 ? relax_arg : ctl->relax);
   const int nb = gridDim.x;
   int tile = blockIdx.x;
   if (xcd_bands && (nb & 7) == 0) tile = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
   double rmax = 0.0, pmax = 0.0;
-  sor_tile<T, TX, TY, S, NT, CHECK>(pin, pout, F, n, pitch, tile, tiles_x, w, sp, rmax, pmax);
+  sor_tile<T, TX, TY, S, NT>(pin, pout, F, n, pitch, tile, tiles_x, w, sp, CHECK, rmax, pmax);
   if (CHECK) check_and_decide_reduced<NT>(ctl, part, rmax, pmax, -1);
 }
 
@@ -569,8 +645,8 @@ __global__ __launch_bounds__(NT) void k_batch64(const BatchMember* __restrict__ 
                                                 BatchCtl* __restrict__ bc,
                                                 unsigned int* __restrict__ flags,
                                                 long long spin_ticks) {
-  using G = SorGeom<double, TX, TY, S>;
-  __shared__ double sp[G::SINK + 64];
+  using G = SorGeom<double, TX, TY, S, NT>;
+  __shared__ double sp[G::SLOTS];
   const unsigned int nb = gridDim.x;
   unsigned int gen = batch_epoch(bc);
   while (any_running(mem, count)) {
@@ -585,16 +661,13 @@ __global__ __launch_bounds__(NT) void k_batch64(const BatchMember* __restrict__ 
         const double* pin = fwd ? m.psi : m.psi_b;
         double* pout = fwd ? m.psi_b : m.psi;
         double rmax = 0.0, pmax = 0.0;
-        if (check) {
-          sor_tile<double, TX, TY, S, NT, true>(pin, pout, m.F, m.n, m.pitch, lt, m.tiles_x, w,
-                                                sp, rmax, pmax);
-          if (threadIdx.x == 0) {
-            m.part[2 * lt] = rmax;
-            m.part[2 * lt + 1] = pmax;
-          }
-        } else {
-          sor_tile<double, TX, TY, S, NT, false>(pin, pout, m.F, m.n, m.pitch, lt, m.tiles_x, w,
-                                                 sp, rmax, pmax);
+        // one inlined tile body for both kinds of round keeps the register
+        // budget of 1024-thread blocks
+        sor_tile<double, TX, TY, S, NT>(pin, pout, m.F, m.n, m.pitch, lt, m.tiles_x, w, sp, check,
+                                        rmax, pmax);
+        if (check && threadIdx.x == 0) {
+          m.part[2 * lt] = rmax;
+          m.part[2 * lt + 1] = pmax;
         }
         __syncthreads();
       }
@@ -612,8 +685,8 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
                                                     BatchCtl* __restrict__ bc,
                                                     unsigned int* __restrict__ flags,
                                                     long long spin_ticks) {
-  using G = SorGeom<float, TX, TY, S>;
-  __shared__ float sp[G::SINK + 64];
+  using G = SorGeom<float, TX, TY, S, NT>;
+  __shared__ float sp[G::SLOTS];
   const unsigned int nb = gridDim.x;
   unsigned int gen = batch_epoch(bc);
   for (;;) {
@@ -660,9 +733,8 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
         if (load_state(m.ctl) != SOLVE_RUN) continue;
         const float w = (r >= 2 * (inner_pairs - 1)) ? 1.0f : (float)m.ctl->relax;
         double rm = 0.0, pm = 0.0;
-        sor_tile<float, TX, TY, S, NT, false>(fwd ? m.d32a : m.d32b, fwd ? m.d32b : m.d32a,
-                                              m.R32, m.n, m.pitch, t - m.tile0, m.tiles_x, w,
-                                              sp, rm, pm);
+        sor_tile<float, TX, TY, S, NT>(fwd ? m.d32a : m.d32b, fwd ? m.d32b : m.d32a, m.R32, m.n,
+                                       m.pitch, t - m.tile0, m.tiles_x, w, sp, false, rm, pm);
         __syncthreads();
       }
       if (!grid_sync(bc, flags, nb, gen, spin_ticks)) return;
@@ -1134,6 +1206,7 @@ hipError_t sor_launch(const T* pin, T* pout, const T* F, int n, int pitch, Poiss
   X(64, 64, 2, 512)            \
   X(64, 64, 4, 512)            \
   X(64, 64, 4, 1024)           \
+  X(64, 64, 4, 768)            \
   X(96, 64, 2, 1024)           \
   X(96, 64, 3, 1024)
 
@@ -1239,7 +1312,10 @@ int sor_max_blocks(int n) { return ((n + 31) / 32) * ((n + 31) / 32); }
   X(32, 32, 1, 256)              \
   X(64, 32, 2, 512)              \
   X(64, 64, 2, 512)              \
-  X(64, 64, 4, 512)
+  X(64, 64, 3, 512)              \
+  X(64, 32, 3, 512)              \
+  X(64, 32, 4, 512)              \
+  X(64, 64, 3, 768)
 
 #define CAV_BATCH_CONFIGS_F32(X) \
   X(32, 32, 1, 256)              \

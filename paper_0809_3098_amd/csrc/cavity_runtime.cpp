@@ -136,7 +136,7 @@ struct cavity_s {
   // ---- execution of the Poisson solves
   int exec = CAVITY_EXEC_STREAM;
   bool mixed = false;                   // batch precision (all members agree)
-  cav::SorConfig bcfg64{64, 64, 2, 512, 0};
+  cav::SorConfig bcfg64{64, 64, 3, 768, 0};
   cav::SorConfig bcfg32{64, 64, 4, 1024, 0};
   int b_ppc = 1;                        // FP64: launch-pairs per check
   int b_inner_pairs = 1;                // mixed: FP32 launch-pairs per round
@@ -223,18 +223,22 @@ int derive(const cavity_params& p, Member& m) {
   // A stalled over-relaxation sits at its rounding floor; allow several
   // residual halvings' worth of sweeps (about 0.11 (n-1) each) before polishing.
   m.stall_window = std::max<long long>(64, 2LL * p.n);
-  // tiles: small grids favour more, smaller blocks
-  // (measured on MI355X: 64x64 tiles with 4 sweeps per launch and 1024
-  // threads are fastest from 1024^2 up; XCD-banded tile order helps while the
-  // tile count is a multiple of 8)
+  // tiles: small grids favour more, smaller blocks.  Measured on MI355X:
+  // at 1024^2, 64 x 64 tiles with 4 (FP64) or 6 (FP32) sweeps per launch and
+  // 1024 threads; at 4096^2, 96 x 64 tiles with 3 sweeps per launch; the
+  // XCD-banded tile order helps while the tile count is a multiple of 8.
+  auto banded = [&](int tx, int ty) {
+    return (((p.n + tx - 1) / tx) * ((p.n + ty - 1) / ty)) % 8 == 0 ? 1 : 0;
+  };
   if (p.n <= 320) {
     m.cfg64 = {32, 32, 1, 256, 0};
     m.cfg32 = {32, 32, 1, 256, 0};
+  } else if (p.n <= 2048) {
+    m.cfg64 = {64, 64, 4, 1024, banded(64, 64)};
+    m.cfg32 = {64, 64, 6, 1024, banded(64, 64)};
   } else {
-    const int tiles = ((p.n + 63) / 64) * ((p.n + 63) / 64);
-    const int xcd = (tiles % 8 == 0 && p.n <= 2048) ? 1 : 0;
-    m.cfg64 = {64, 64, 4, 1024, xcd};
-    m.cfg32 = {64, 64, 4, 1024, xcd};
+    m.cfg64 = {96, 64, 3, 1024, banded(96, 64)};
+    m.cfg32 = {96, 64, 3, 1024, banded(96, 64)};
   }
   set_schedule(m, std::min(32, std::max(4, p.n / 32)), (int)std::ceil(1.5 * (p.n - 1)));
   return CAVITY_OK;
@@ -1283,7 +1287,7 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
     int inner = 0;
     for (const Member& m : h->m) inner = std::max(inner, m.inner_sweeps);
     const int small = h->m[0].n <= 320 && count == 1;
-    h->bcfg64 = small ? cav::SorConfig{32, 32, 1, 256, 0} : cav::SorConfig{64, 64, 2, 512, 0};
+    h->bcfg64 = small ? cav::SorConfig{32, 32, 1, 256, 0} : cav::SorConfig{64, 64, 3, 768, 0};
     h->bcfg32 = small ? cav::SorConfig{32, 32, 1, 256, 0} : cav::SorConfig{64, 64, 4, 1024, 0};
     h->b_ppc = std::max(1, 32 / (2 * h->bcfg64.s));
     h->b_inner_pairs = std::max(1, (inner + 2 * h->bcfg32.s - 1) / (2 * h->bcfg32.s));
@@ -1574,6 +1578,8 @@ int cavity_autotune(cavity_t h, int32_t idx, const char* cache_path, cavity_tuni
   if ((rc = cavity_get_tuning(h, idx, &t)) != CAVITY_OK) return rc;
   struct Cand { int tx, ty, s, nt, xcd; };
   static const std::vector<Cand> k64 = {{32, 32, 1, 256, 0}, {32, 32, 2, 256, 0}, {64, 32, 2, 512, 0},
+                             {64, 32, 3, 512, 0},  {64, 32, 4, 512, 0},  {64, 64, 3, 512, 0},
+                             {64, 64, 3, 768, 0},  {64, 64, 4, 768, 0},
                              {64, 64, 1, 1024, 0}, {64, 64, 2, 1024, 0}, {64, 64, 3, 1024, 0},
                              {64, 64, 2, 512, 0},  {64, 64, 4, 512, 0},  {64, 64, 4, 1024, 0},
                              {96, 64, 2, 1024, 0},
