@@ -18,12 +18,11 @@ enum SolveState : int {
 
 // Device-resident control block of one cavity's Poisson solve.  Every sweep
 // launch reads `state` first and returns at once unless it is SOLVE_RUN, so
-// the host may enqueue more sweeps than needed without waiting.  The block
-// that finishes a checking launch last (ticket) takes the decision.
+// the host may enqueue more sweeps than needed without waiting.  A checking
+// launch leaves per-block maxima; a one-block decision kernel that follows it
+// on the stream (or a block of the batched kernel after a grid barrier)
+// reduces them and takes the decision.
 struct alignas(128) PoissonCtl {
-  unsigned long long rbits;   // max |g - psi| of the running check, as bits
-  unsigned long long pbits;   // max |psi| of the running check, as bits
-  unsigned int ticket;        // blocks of the running check that are done
   int state;                  // SolveState
   int phase;                  // 0 = over-relaxation, 1 = Gauss-Seidel polish
   int polish_left;            // polish checks still allowed

@@ -98,69 +98,6 @@ __device__ void decide(PoissonCtl* c, double r, double pm, long long sweeps_done
   c->state = st;
 }
 
-// As check_and_decide, for maxima already reduced over the block (valid in
-// thread 0).
-template <int NT>
-__device__ void check_and_decide_reduced(PoissonCtl* ctl, double* part, double rmax, double pmax,
-                                         long long sweeps_done) {
-  __shared__ int s_last;
-  const unsigned int nb = gridDim.x * gridDim.y;
-  const unsigned int bid = blockIdx.y * gridDim.x + blockIdx.x;
-  if (threadIdx.x == 0) {
-    part[2 * bid] = rmax;
-    part[2 * bid + 1] = pmax;
-    __threadfence();
-    const unsigned int t = atomicAdd(&ctl->ticket, 1u);
-    s_last = (t == nb - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  double r = 0.0, p = 0.0;
-  for (unsigned int k = threadIdx.x; k < nb; k += NT) {
-    r = fmax(r, part[2 * k]);
-    p = fmax(p, part[2 * k + 1]);
-  }
-  block_max2<NT>(r, p);
-  if (threadIdx.x == 0) {
-    ctl->ticket = 0u;
-    decide(ctl, r, p, sweeps_done < 0 ? ctl->sweeps_per_check : sweeps_done);
-  }
-}
-
-// Called by every thread of every block of a checking launch with its local
-// maxima.  Each block stores its maxima in `part` and takes one ticket; the
-// block holding the last ticket reduces all partial maxima and decides.  One
-// same-address atomic per block keeps the cost flat in the block count.
-template <int NT>
-__device__ void check_and_decide(PoissonCtl* ctl, double* part, double rmax, double pmax,
-                                 long long sweeps_done) {
-  __shared__ int s_last;
-  block_max2<NT>(rmax, pmax);
-  const unsigned int nb = gridDim.x * gridDim.y;
-  const unsigned int bid = blockIdx.y * gridDim.x + blockIdx.x;
-  if (threadIdx.x == 0) {
-    part[2 * bid] = rmax;
-    part[2 * bid + 1] = pmax;
-    __threadfence();
-    const unsigned int t = atomicAdd(&ctl->ticket, 1u);
-    s_last = (t == nb - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  double r = 0.0, p = 0.0;
-  for (unsigned int k = threadIdx.x; k < nb; k += NT) {
-    r = fmax(r, part[2 * k]);
-    p = fmax(p, part[2 * k + 1]);
-  }
-  block_max2<NT>(r, p);
-  if (threadIdx.x == 0) {
-    ctl->ticket = 0u;
-    decide(ctl, r, p, sweeps_done < 0 ? ctl->sweeps_per_check : sweeps_done);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Temporally blocked four-colour relaxation of eq. (SequationFinal).
 //
@@ -517,7 +454,30 @@ __global__ __launch_bounds__(NT) void k_sor(const T* __restrict__ pin, T* __rest
   if (xcd_bands && (nb & 7) == 0) tile = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
   double rmax = 0.0, pmax = 0.0;
   sor_tile<T, TX, TY, S, NT>(pin, pout, F, n, pitch, tile, tiles_x, w, sp, CHECK, rmax, pmax);
-  if (CHECK) check_and_decide_reduced<NT>(ctl, part, rmax, pmax, -1);
+  // A checking launch only leaves its per-block maxima; k_decide, the next
+  // launch on the stream, reduces them.  The kernel boundary orders the
+  // stores, so no block pays for a device-wide release fence.
+  if (CHECK && threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rmax;
+    part[2 * blockIdx.x + 1] = pmax;
+  }
+}
+
+// The decision after a checking launch of nb blocks (one block).  A solve
+// that had already stopped launched no sweep, and its partial maxima are
+// stale: it is left alone.
+// sweeps_done < 0 counts the control block's sweeps per check.
+__global__ __launch_bounds__(256) void k_decide(PoissonCtl* __restrict__ ctl,
+                                                const double* __restrict__ part, int nb,
+                                                long long sweeps_done) {
+  if (ctl->state != SOLVE_RUN) return;
+  double r = 0.0, p = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) {
+    r = fmax(r, part[2 * k]);
+    p = fmax(p, part[2 * k + 1]);
+  }
+  block_max2<256>(r, p);
+  if (threadIdx.x == 0) decide(ctl, r, p, sweeps_done < 0 ? ctl->sweeps_per_check : sweeps_done);
 }
 
 // ---------------------------------------------------------------------------
@@ -962,9 +922,6 @@ __global__ __launch_bounds__(kBlock) void k_thom(const double* __restrict__ psi,
 __global__ void k_ctl_reset(PoissonCtl* c, double relax, double tol_hat, long long max_sweeps,
                             long long stall_window, long long sweeps_per_check) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  c->rbits = 0ull;
-  c->pbits = 0ull;
-  c->ticket = 0u;
   c->state = SOLVE_RUN;
   c->phase = 0;
   c->polish_left = 0;
@@ -992,9 +949,8 @@ __global__ __launch_bounds__(kBlock) void k_resid64(const double* __restrict__ p
                                                     const double* __restrict__ F,
                                                     float* __restrict__ R32,
                                                     float* __restrict__ d32, int n, int pitch,
-                                                    PoissonCtl* __restrict__ ctl,
-                                                    double* __restrict__ part,
-                                                    long long sweeps_done) {
+                                                    const PoissonCtl* __restrict__ ctl,
+                                                    double* __restrict__ part) {
   if (ctl->state != SOLVE_RUN) return;
   double rmax = 0.0, pmax = 0.0;
   const int m = n - 2;
@@ -1016,7 +972,12 @@ __global__ __launch_bounds__(kBlock) void k_resid64(const double* __restrict__ p
     rmax = fmax(rmax, mag(r));
     pmax = fmax(pmax, mag(psi[p]));
   }
-  check_and_decide<kBlock>(ctl, part, rmax, pmax, sweeps_done);
+  // per-block maxima only; k_decide follows on the stream
+  block_max2<kBlock>(rmax, pmax);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rmax;
+    part[2 * blockIdx.x + 1] = pmax;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_refine(double* __restrict__ psi,
@@ -1185,10 +1146,11 @@ hipError_t sor_launch(const T* pin, T* pout, const T* F, int n, int pitch, Poiss
                       double* part, int check, int xcd_bands, double relax, hipStream_t st) {
   const int tx = (n + TX - 1) / TX, ty = (n + TY - 1) / TY;
   const dim3 grid(tx * ty);
-  if (check)
+  if (check) {
     hipLaunchKernelGGL((k_sor<T, TX, TY, S, NT, true>), grid, dim3(NT), 0, st, pin, pout, F, n,
                        pitch, ctl, part, tx, xcd_bands, relax);
-  else
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, st, ctl, part, (int)grid.x, -1LL);
+  } else
     hipLaunchKernelGGL((k_sor<T, TX, TY, S, NT, false>), grid, dim3(NT), 0, st, pin, pout, F, n,
                        pitch, ctl, part, tx, xcd_bands, relax);
   return hipGetLastError();
@@ -1394,7 +1356,8 @@ hipError_t launch_resid64(const double* psi, const double* F, float* R32, float*
   const long long cells = (long long)(n - 2) * (n - 2);
   const int blocks = (int)std::min<long long>(kResidBlocks, (cells + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_resid64, dim3(blocks), dim3(kBlock), 0, st, psi, F, R32, d32, n, pitch,
-                     ctl, part, sweeps_done);
+                     ctl, part);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, st, ctl, part, blocks, sweeps_done);
   return hipGetLastError();
 }
 
