@@ -124,7 +124,7 @@ def main():
                     help="instead of the bench: run the coarse-grid cavities of the grid "
                          "dependence study towards a steady state, one line per chunk")
     ap.add_argument("--study-steps", type=int, default=200000)
-    ap.add_argument("--study-chunk", type=int, default=5000)
+    ap.add_argument("--study-chunk", type=int, default=1000)
     ap.add_argument("--study-seconds", type=float, default=240.0,
                     help="wall-clock limit per cavity of the grid study")
     args = ap.parse_args()
@@ -174,6 +174,9 @@ def main():
             for r, m in wl["members"]:
                 cav = Cavity(Params(n=m, re=r, dt=wl["dt"], poisson_tol=wl["tol"]),
                              device="cuda:0", stream=stream)
+                # the multigrid solver reaches the same discrete solution with far
+                # fewer launches per stage than SOR on these small grids
+                cav.set_tuning(solver=CAVITY_SOLVER_MG)
                 t0 = time.perf_counter()
                 done, first, outcome = 0, -1, "max_steps"
                 while done < args.study_steps:
@@ -201,7 +204,8 @@ def main():
                     if time.perf_counter() - t0 > args.study_seconds:
                         outcome = "time limit"
                         break
-                summary = {"n": m, "re": r, "outcome": outcome, "steady_step": first,
+                summary = {"n": m, "re": r, "dt": wl["dt"], "solver": "multigrid",
+                           "outcome": outcome, "steady_step": first,
                            "steps": done, "t": round(done * wl["dt"], 6),
                            "wall_s": round(time.perf_counter() - t0, 2)}
                 f.write(json.dumps({"summary": summary}) + "\n")
@@ -276,10 +280,13 @@ def main():
             "value": round(n * n * args.steps / el / 1e6, 4),
             "ms_per_step": round(1e3 * el / args.steps, 3),
             "sweeps_per_stage": st[0]["sweeps_last_step"] / 5, "steps": args.steps}
-        # batched six-cavity Reynolds sweep vs one by one
-        b = WORKLOADS["re_sweep6"]
-        cells = sum(m * m for _, m in b["members"])
-        for label, prec_b in (("fp64", CAVITY_FP64), ("mixed", CAVITY_MIXED)):
+        # batched Reynolds sweeps vs one cavity at a time: six cavities 256^2..1024^2
+        # (FP64 and mixed) and sixteen 128^2 cavities (FP64)
+        for wname, label, prec_b in (("re_sweep6", "fp64", CAVITY_FP64),
+                                     ("re_sweep6", "mixed", CAVITY_MIXED),
+                                     ("re_scan16_small", "fp64", CAVITY_FP64)):
+            b = WORKLOADS[wname]
+            cells = sum(m * m for _, m in b["members"])
             cb = Cavity([Params(n=m, re=r, poisson_tol=b["tol"], precision=prec_b)
                          for r, m in b["members"]], device="cuda:0", stream=stream)
             el, _ = _timed_steps(torch, cb, args.extra_steps, 1)
@@ -291,7 +298,7 @@ def main():
                 e1, _ = _timed_steps(torch, cs, args.extra_steps, 1)
                 seq += e1
                 cs.close()
-            extras[f"re_sweep6_{label}"] = {
+            extras[f"{wname}_{label}"] = {
                 "cells": cells,
                 "batched_graph_mcell_steps_s": round(cells * args.extra_steps / el / 1e6, 4),
                 "sequential_stream_mcell_steps_s": round(cells * args.extra_steps / seq / 1e6, 4),

@@ -123,11 +123,17 @@ __device__ void decide(PoissonCtl* c, double r, double pm, long long sweeps_done
 // column per neighbour row, the other-side column from the adjacent lane by
 // a DPP wavefront shift, and walking up the strip reuses the row below.
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TY, int S, int NT>
+// HX = 2 widens the halo by the ring that the tile's residual reads: after
+// 4S passes the nodes at least 4S from the region edge are exact, which is
+// all a launch that only sweeps needs (H = 4S); evaluating the residual of
+// the tile needs its first ring exact too (H = 4S + 2, even for the parity
+// planes).
+template <typename T, int TX, int TY, int S, int NT, int HX>
 struct SorGeom {
   static_assert(TX % 2 == 0 && TY % 2 == 0, "tile sizes must be even");
   static_assert(NT % 64 == 0, "whole wavefronts");
-  static constexpr int H = 4 * S + 2;
+  static_assert(HX == 0 || HX == 2, "halo extra is 0 or 2");
+  static constexpr int H = 4 * S + HX;
   static constexpr int RX = TX + 2 * H;
   static constexpr int RY = TY + 2 * H;
   static constexpr int RXH = RX / 2;
@@ -175,12 +181,12 @@ template <> struct Pair<float> { using type = float2; };
 
 // One colour pass C (parity class (C & 1, C >> 1)) of pass number k over the
 // nodes this thread owns.  sp points at the first plane.
-template <typename T, int TX, int TY, int S, int NT, int C>
-__device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][SorGeom<T, TX, TY, S, NT>::K],
-                                            const T (&fv)[4][SorGeom<T, TX, TY, S, NT>::K],
+template <typename T, int TX, int TY, int S, int NT, int HX, int C>
+__device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
+                                            const T (&fv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
                                             int k, int lxd0, int lxd1, int lyd0, int lyd1,
                                             int lane, int b0, T w) {
-  using G = SorGeom<T, TX, TY, S, NT>;
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
   constexpr int K = G::K;
   constexpr int cx = C & 1, cy = C >> 1;
   const int lxlo = max(k, lxd0), lxhi = min(G::RX - 1 - k, lxd1);
@@ -246,13 +252,13 @@ __device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][SorGeom<T, TX, TY,
 // Residual of colour C over the tile's own interior nodes after the sweeps:
 // max |g - psi| and max |psi| accumulated into rmax / pmax.  Same neighbour
 // reads and the same arithmetic as the update, no stores.
-template <typename T, int TX, int TY, int S, int NT, int C>
+template <typename T, int TX, int TY, int S, int NT, int HX, int C>
 __device__ __forceinline__ void residual_pass(const T* pl,
-                                              const T (&pv)[4][SorGeom<T, TX, TY, S, NT>::K],
-                                              const T (&fv)[4][SorGeom<T, TX, TY, S, NT>::K],
+                                              const T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
+                                              const T (&fv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
                                               int lxd0, int lxd1, int lyd0, int lyd1, int lane,
                                               int b0, double& rmax, double& pmax) {
-  using G = SorGeom<T, TX, TY, S, NT>;
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
   constexpr int K = G::K;
   constexpr int cx = C & 1, cy = C >> 1;
   const int lxlo = max(G::H, lxd0), lxhi = min(G::H + TX - 1, lxd1);
@@ -301,12 +307,12 @@ __device__ __forceinline__ void residual_pass(const T* pl,
 // batched kernel.  sp is the block's LDS (four parity planes of psi).  With
 // CHECK the block-wide maxima of |g - psi| and |psi| over the tile are
 // returned in thread 0's rmax / pmax.
-template <typename T, int TX, int TY, int S, int NT>
+template <typename T, int TX, int TY, int S, int NT, int HX>
 __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restrict__ pout,
                                          const T* __restrict__ F, int n, int pitch, int tile,
                                          int tiles_x, T w, T* sp, bool CHECK, double& rmax_out,
                                          double& pmax_out) {
-  using G = SorGeom<T, TX, TY, S, NT>;
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
   using T2 = typename Pair<T>::type;
   constexpr int K = G::K;
   T* const pl = sp + G::BASE;  // first parity plane
@@ -393,10 +399,10 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
 #pragma unroll 1
   for (int s = 0; s < S; ++s) {
     const int k = 4 * s;
-    colour_pass<T, TX, TY, S, NT, 0>(pl, pv, fv, k + 1, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
-    colour_pass<T, TX, TY, S, NT, 1>(pl, pv, fv, k + 2, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
-    colour_pass<T, TX, TY, S, NT, 2>(pl, pv, fv, k + 3, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
-    colour_pass<T, TX, TY, S, NT, 3>(pl, pv, fv, k + 4, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    colour_pass<T, TX, TY, S, NT, HX, 0>(pl, pv, fv, k + 1, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    colour_pass<T, TX, TY, S, NT, HX, 1>(pl, pv, fv, k + 2, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    colour_pass<T, TX, TY, S, NT, HX, 2>(pl, pv, fv, k + 3, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    colour_pass<T, TX, TY, S, NT, HX, 3>(pl, pv, fv, k + 4, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
   }
 
   // Write the owned tile nodes, a pair (x even, x odd) per store where both
@@ -430,10 +436,10 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
     }
   }
   if (CHECK) {
-    residual_pass<T, TX, TY, S, NT, 0>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
-    residual_pass<T, TX, TY, S, NT, 1>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
-    residual_pass<T, TX, TY, S, NT, 2>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
-    residual_pass<T, TX, TY, S, NT, 3>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
+    residual_pass<T, TX, TY, S, NT, HX, 0>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
+    residual_pass<T, TX, TY, S, NT, HX, 1>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
+    residual_pass<T, TX, TY, S, NT, HX, 2>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
+    residual_pass<T, TX, TY, S, NT, HX, 3>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
   }
   if (CHECK) block_max2<NT>(rmax, pmax);
   rmax_out = rmax;
@@ -445,7 +451,8 @@ __global__ __launch_bounds__(NT) void k_sor(const T* __restrict__ pin, T* __rest
                                             const T* __restrict__ F, int n, int pitch,
                                             PoissonCtl* __restrict__ ctl, double* __restrict__ part,
                                             int tiles_x, int xcd_bands, double relax_arg) {
-  using G = SorGeom<T, TX, TY, S, NT>;
+  constexpr int HX = CHECK ? 2 : 0;
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
   __shared__ T sp[G::SLOTS];
   if (ctl->state != SOLVE_RUN) return;
   const T w = (T)(relax_arg > 0.0 ? relax_arg : ctl->relax);
@@ -453,7 +460,8 @@ __global__ __launch_bounds__(NT) void k_sor(const T* __restrict__ pin, T* __rest
   int tile = blockIdx.x;
   if (xcd_bands && (nb & 7) == 0) tile = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
   double rmax = 0.0, pmax = 0.0;
-  sor_tile<T, TX, TY, S, NT>(pin, pout, F, n, pitch, tile, tiles_x, w, sp, CHECK, rmax, pmax);
+  sor_tile<T, TX, TY, S, NT, HX>(pin, pout, F, n, pitch, tile, tiles_x, w, sp, CHECK, rmax,
+                                 pmax);
   // A checking launch only leaves its per-block maxima; k_decide, the next
   // launch on the stream, reduces them.  The kernel boundary orders the
   // stores, so no block pays for a device-wide release fence.
@@ -605,7 +613,7 @@ __global__ __launch_bounds__(NT) void k_batch64(const BatchMember* __restrict__ 
                                                 BatchCtl* __restrict__ bc,
                                                 unsigned int* __restrict__ flags,
                                                 long long spin_ticks) {
-  using G = SorGeom<double, TX, TY, S, NT>;
+  using G = SorGeom<double, TX, TY, S, NT, 2>;  // rounds may check
   __shared__ double sp[G::SLOTS];
   const unsigned int nb = gridDim.x;
   unsigned int gen = batch_epoch(bc);
@@ -623,8 +631,8 @@ __global__ __launch_bounds__(NT) void k_batch64(const BatchMember* __restrict__ 
         double rmax = 0.0, pmax = 0.0;
         // one inlined tile body for both kinds of round keeps the register
         // budget of 1024-thread blocks
-        sor_tile<double, TX, TY, S, NT>(pin, pout, m.F, m.n, m.pitch, lt, m.tiles_x, w, sp, check,
-                                        rmax, pmax);
+        sor_tile<double, TX, TY, S, NT, 2>(pin, pout, m.F, m.n, m.pitch, lt, m.tiles_x, w, sp,
+                                           check, rmax, pmax);
         if (check && threadIdx.x == 0) {
           m.part[2 * lt] = rmax;
           m.part[2 * lt + 1] = pmax;
@@ -645,7 +653,7 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
                                                     BatchCtl* __restrict__ bc,
                                                     unsigned int* __restrict__ flags,
                                                     long long spin_ticks) {
-  using G = SorGeom<float, TX, TY, S, NT>;
+  using G = SorGeom<float, TX, TY, S, NT, 0>;  // correction sweeps never check
   __shared__ float sp[G::SLOTS];
   const unsigned int nb = gridDim.x;
   unsigned int gen = batch_epoch(bc);
@@ -693,8 +701,9 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
         if (load_state(m.ctl) != SOLVE_RUN) continue;
         const float w = (r >= 2 * (inner_pairs - 1)) ? 1.0f : (float)m.ctl->relax;
         double rm = 0.0, pm = 0.0;
-        sor_tile<float, TX, TY, S, NT>(fwd ? m.d32a : m.d32b, fwd ? m.d32b : m.d32a, m.R32, m.n,
-                                       m.pitch, t - m.tile0, m.tiles_x, w, sp, false, rm, pm);
+        sor_tile<float, TX, TY, S, NT, 0>(fwd ? m.d32a : m.d32b, fwd ? m.d32b : m.d32a, m.R32,
+                                          m.n, m.pitch, t - m.tile0, m.tiles_x, w, sp, false, rm,
+                                          pm);
         __syncthreads();
       }
       if (!grid_sync(bc, flags, nb, gen, spin_ticks)) return;

@@ -15,6 +15,9 @@ WORKLOADS = {
     "re_sweep6": dict(members=[(5000.0, 256), (10000.0, 512), (15000.0, 768),
                                (20000.0, 1024), (25000.0, 1024), (30000.0, 1024)],
                       steps=1000, tol=1e-10, init="rest"),
+    # many small cavities (a parameter scan at low resolution): 16 x 128^2, Re 500..8000
+    "re_scan16_small": dict(members=[(500.0 * (k + 1), 128) for k in range(16)],
+                            steps=200, tol=1e-10, init="rest"),
     # coarse grids of Sec. 4: 220^2 for Re 5e3 and 1e4, 300^2 for 1.5e4, and 300^2 at 2e4,
     # where the paper found no solution on that grid; dt as in Table tab:grid
     "grid_dependence": dict(members=[(5000.0, 220), (10000.0, 220), (15000.0, 300),
