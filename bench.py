@@ -31,7 +31,7 @@ METRIC = "Mcell-steps/s at 1024² (FP64 vs mixed+refine), achieved HBM GB/s vs p
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SWEEP_NODE = {0: 24.0, 1: 12.0}   # FP64 / FP32: psi in, rhs in, psi out
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sor_traffic.json")
-EXEC = {"stream": 0, "persistent": 1, "graph": 2}
+EXEC = {"stream": 0, "persistent": 1, "graph": 2, "resident": 3}
 
 
 def _kernel_source_hash() -> str:
@@ -253,10 +253,18 @@ def main():
         mg["vcycles_per_stage"] = mg["sweeps_per_stage"] / 4 if mg["sweeps_per_stage"] else None
         cmg.close()
         extras["multigrid_1024_re1e4_fp64"] = mg
-        # the persistent-kernel execution of the headline workload
+        # the persistent-kernel and resident-solve executions of the headline workload
         cp, _, pers = single(args.workload, args.extra_steps, 1, "persistent")
         cp.close()
         extras["persistent_1024_re1e4_fp64"] = pers
+        if args.exec != "resident":
+            cr, _, res = single(args.workload, args.steps, args.warmup, "resident")
+            cr.close()
+            extras["resident_1024_re1e4_fp64"] = res
+        if args.exec != "stream":
+            cs_, _, strm = single(args.workload, args.steps, args.warmup, "stream")
+            cs_.close()
+            extras["stream_1024_re1e4_fp64"] = strm
         # mixed + refinement at 1024^2, Re 3e4
         cavm, _, mixed = single("cavity1024_re3e4_mixed", args.extra_steps, 1, args.exec)
         mixed["roofline_fp32_sweep"] = _sweep_roofline(torch, cavm, stream, args.relax_launches,

@@ -276,18 +276,34 @@ int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t);
  *                           of the handle (tile list over all cavities, grid
  *                           barriers between sweep rounds, per-cavity stopping
  *                           decisions on the device); one readback per step.
+ *   CAVITY_EXEC_RESIDENT    as STREAM, but an FP64 SOR solve of a cavity whose
+ *                           tiles fit the device at once runs as one launch:
+ *                           one block per tile for the whole solve keeps its
+ *                           tile on chip and swaps halos with its neighbours
+ *                           after every few sweeps; the residual is checked as
+ *                           often as in STREAM and the solve stops two rounds
+ *                           of sweeps after the check that ends it (so its
+ *                           sweep counts, and results to within the
+ *                           tolerance, differ from STREAM).  Other cavities
+ *                           (mixed, multigrid, coupled, too large) run as in
+ *                           STREAM.
  *   CAVITY_EXEC_GRAPH       as PERSISTENT, with the whole step (five stages)
  *                           captured once per buffer parity in a hipGraph and
  *                           replayed (default for count > 1).  When every
  *                           cavity is in the coupled mode (fixed_sweeps > 0)
  *                           the graph holds the per-launch sweeps instead.
  * Both persistent modes need one precision for all cavities and the SOR
- * solver; a coupled cavity allows STREAM, and GRAPH only if all cavities of
- * the handle are coupled (EINVAL otherwise).  With the same tile sweeps per
- * launch, check spacing and relaxation, all three modes give bitwise
- * identical results.
+ * solver; a coupled cavity allows STREAM and RESIDENT, and GRAPH only if all
+ * cavities of the handle are coupled (EINVAL otherwise).  With the same tile
+ * sweeps per launch, check spacing and relaxation, STREAM, PERSISTENT and
+ * GRAPH give bitwise identical results.
  */
-enum cavity_exec { CAVITY_EXEC_STREAM = 0, CAVITY_EXEC_PERSISTENT = 1, CAVITY_EXEC_GRAPH = 2 };
+enum cavity_exec {
+  CAVITY_EXEC_STREAM = 0,
+  CAVITY_EXEC_PERSISTENT = 1,
+  CAVITY_EXEC_GRAPH = 2,
+  CAVITY_EXEC_RESIDENT = 3
+};
 int cavity_set_exec(cavity_t h, int32_t mode);
 int cavity_get_exec(cavity_t h, int32_t* mode);
 

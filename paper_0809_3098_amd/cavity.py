@@ -36,6 +36,7 @@ CAVITY_MIXED = 1
 CAVITY_EXEC_STREAM = 0
 CAVITY_EXEC_PERSISTENT = 1
 CAVITY_EXEC_GRAPH = 2
+CAVITY_EXEC_RESIDENT = 3
 CAVITY_SOLVER_SOR = 0
 CAVITY_SOLVER_MG = 1
 

@@ -38,7 +38,7 @@ struct alignas(128) PoissonCtl {
   long long stall_window;     // sweeps without halving that mean stagnation
   long long sweeps_per_check; // sweeps between two checks
   int floor_limited;
-  int pad0;
+  int werror;                 // 1: a wait of a resident solve timed out
   // Totals over every solve since the handle was created (never reset by a
   // solve), read by the host once per call.
   long long total_sweeps;
@@ -77,6 +77,16 @@ struct alignas(128) BatchCtl {
 constexpr int kMaxBatchGrid = 4096;        // blocks of a persistent launch
 constexpr int kFlagStride = 32;            // words between two arrival flags
 
+// Decision exchange of a resident solve (one per cavity).  Slot c % 2 holds
+// the decision of residual check c once tag[c % 2] == c + 1.
+struct alignas(128) ResidentCtl {
+  unsigned int tag[2];
+  int state[2];
+  double relax[2];
+  int error;           // 1: a wait timed out (blocks not co-resident)
+  int pad;
+};
+
 // Tile configuration of the temporally blocked four-colour sweep.
 struct SorConfig {
   int tx, ty;      // output tile (nodes)
@@ -87,6 +97,11 @@ struct SorConfig {
 
 // Whether (tx, ty, s, nt) is one of the compiled sweep kernels.
 bool sor_config_supported(const SorConfig& c, bool fp32);
+// Whether a resident solve exists for this tile shape and fits the device
+// with one co-resident block per tile.
+bool resident_supported(const SorConfig& c, int n, int device);
+// Arrival flags of a resident solve: one 128-byte line per tile.
+size_t resident_flag_bytes(int n);
 // Upper bound on the blocks of any sweep launch (smallest tile) and of the
 // residual kernel: sizes the partial-maximum array.
 int sor_max_blocks(int n);
@@ -129,6 +144,18 @@ hipError_t launch_sor64(const SorConfig& cfg, const double* psi_in, double* psi_
                         int check, hipStream_t st);
 hipError_t launch_sor32(const SorConfig& cfg, const float* d_in, float* d_out, const float* R,
                         int n, int pitch, PoissonCtl* ctl, double relax, hipStream_t st);
+// A whole FP64 solve in one launch, one block per tile kept resident: tiles
+// exchange halos through psi / psi_b with their neighbours each round of S
+// sweeps; every rounds_per_check rounds the tile residuals are reduced and
+// block 0 decides (the decision takes effect two rounds later).  The result
+// ends in psi.  flags and rctl are cleared by this call; part needs 4 doubles
+// per tile.  Fails with hipErrorInvalidConfiguration when the tiles cannot be
+// co-resident.
+hipError_t launch_sor64_resident(const SorConfig& cfg, double* psi, double* psi_b,
+                                 const double* F, int n, int pitch, PoissonCtl* ctl,
+                                 double* part, unsigned int* flags, ResidentCtl* rctl,
+                                 int rounds_per_check, long long spin_ticks, int device,
+                                 hipStream_t st);
 
 // Persistent batched solves: every member's Poisson solve runs in one launch;
 // blocks sweep the batch's tile list round by round with grid barriers in

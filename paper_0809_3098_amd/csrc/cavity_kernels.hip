@@ -303,61 +303,92 @@ __device__ __forceinline__ void residual_pass(const T* pl,
   }
 }
 
-// One tile of S sweeps, shared by the per-launch kernel and the persistent
-// batched kernel.  sp is the block's LDS (four parity planes of psi).  With
-// CHECK the block-wide maxima of |g - psi| and |psi| over the tile are
-// returned in thread 0's rmax / pmax.
-template <typename T, int TX, int TY, int S, int NT, int HX>
-__device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restrict__ pout,
-                                         const T* __restrict__ F, int n, int pitch, int tile,
-                                         int tiles_x, T w, T* sp, bool CHECK, double& rmax_out,
-                                         double& pmax_out) {
+// Device-coherent 8-byte accesses: agent-scope relaxed atomics, which the
+// compiler emits as loads and stores with the device-scope cache bit, so a
+// value stored on one XCD is seen by a load on another without writing back
+// or invalidating whole L2 caches.
+template <typename T>
+__device__ inline T coh_load(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline void coh_store(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this wavefront's global loads and stores have completed (and its
+// device-scope stores are visible device-wide): s_waitcnt vmcnt(0).
+__device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Phases of a tile, shared by the per-launch, batched and resident kernels.
+// Region coordinates: x0, y0 is the global position of local (0, 0), even.
+
+// psi of the region into the LDS planes, in pairs of nodes (x even, x odd)
+// coalesced along x; the global loads of CHUNK pairs per thread are issued
+// before their LDS stores (all of them by default; fewer keep fewer values
+// live).  RING skips the pairs inside the tile (their LDS values are kept).
+template <typename T, int TX, int TY, int S, int NT, int HX, bool RING, int CHUNK = 0,
+          bool COHERENT = false>
+__device__ __forceinline__ void region_to_lds(const T* __restrict__ pin, int n, int pitch, int x0,
+                                              int y0, T* pl, int tid) {
   using G = SorGeom<T, TX, TY, S, NT, HX>;
   using T2 = typename Pair<T>::type;
-  constexpr int K = G::K;
-  T* const pl = sp + G::BASE;  // first parity plane
-  const int tyi = tile / tiles_x;
-  const int txi = tile - tyi * tiles_x;
-  const int x0 = txi * TX - G::H;  // region origin, even
-  const int y0 = tyi * TY - G::H;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  // the wavefront index is uniform: keeping it in a scalar register makes the
-  // per-row range tests of the colour passes scalar branches
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int b0 = wave * K;         // first owned row of every plane
-
-  // Region load of psi in pairs of nodes (x even, x odd), coalesced along x;
-  // all global loads of a thread are issued before its LDS stores.
   constexpr int RXP = G::RX / 2;
   constexpr int NPAIR = RXP * G::RY;
   constexpr int NL = (NPAIR + NT - 1) / NT;
-  T2 lv[NL];
+  constexpr int CH = (CHUNK > 0 && CHUNK < NL) ? CHUNK : NL;
 #pragma unroll
-  for (int q = 0; q < NL; ++q) {
-    const int idx = tid + q * NT;
-    lv[q].x = lv[q].y = T(0);
-    if (idx < NPAIR) {
+  for (int q0 = 0; q0 < NL; q0 += CH) {
+    T2 lv[CH];
+    bool st[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int idx = tid + (q0 + j) * NT;
+      lv[j].x = lv[j].y = T(0);
       const int ly = idx / RXP;
-      const int gx = x0 + 2 * (idx - ly * RXP), gy = y0 + ly;
-      if ((unsigned)gy < (unsigned)n && gx >= 0) {
-        const size_t g = (size_t)gy * pitch + gx;
-        if (gx + 1 < n) {
-          lv[q] = *reinterpret_cast<const T2*>(pin + g);
-        } else if (gx < n) {
-          lv[q].x = pin[g];
+      const int lx = 2 * (idx - ly * RXP);
+      st[j] = q0 + j < NL && idx < NPAIR &&
+              !(RING && lx >= G::H && lx < G::H + TX && ly >= G::H && ly < G::H + TY);
+      if (st[j]) {
+        const int gx = x0 + lx, gy = y0 + ly;
+        if ((unsigned)gy < (unsigned)n && gx >= 0) {
+          const size_t g = (size_t)gy * pitch + gx;
+          if (COHERENT) {
+            if (gx < n) lv[j].x = coh_load(pin + g);
+            if (gx + 1 < n) lv[j].y = coh_load(pin + g + 1);
+          } else if (gx + 1 < n) {
+            lv[j] = *reinterpret_cast<const T2*>(pin + g);
+          } else if (gx < n) {
+            lv[j].x = pin[g];
+          }
         }
       }
     }
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int idx = tid + (q0 + j) * NT;
+      if (st[j]) {
+        const int ly = idx / RXP;
+        const int o = ((ly & 1) << 1) * G::PLANE + (ly >> 1) * G::RXH + (idx - ly * RXP);
+        pl[o] = lv[j].x;
+        pl[o + G::PLANE] = lv[j].y;
+      }
+    }
   }
-  // Right-hand side of the owned nodes, straight into registers: the nodes
-  // of x parity 0 and 1 at one lane and row are neighbours in memory, so one
-  // pair load serves colours (0, cy) and (1, cy).
-  T fv[4][K];
+}
+
+// Right-hand side of the owned nodes, straight into registers: the nodes of
+// x parity 0 and 1 at one lane and row are neighbours in memory, so one pair
+// load serves colours (0, cy) and (1, cy).
+template <typename T, int TX, int TY, int S, int NT, int HX>
+__device__ __forceinline__ void rhs_to_regs(const T* __restrict__ F, int n, int pitch, int x0,
+                                            int y0, int lane, int b0,
+                                            T (&fv)[4][SorGeom<T, TX, TY, S, NT, HX>::K]) {
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
+  using T2 = typename Pair<T>::type;
 #pragma unroll
   for (int cy = 0; cy < 2; ++cy) {
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
+    for (int r = 0; r < G::K; ++r) {
       const int gx = x0 + 2 * lane, gy = y0 + 2 * (b0 + r) + cy;
       T2 f;
       f.x = f.y = T(0);
@@ -373,29 +404,36 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
       fv[2 * cy + 1][r] = f.y;
     }
   }
-#pragma unroll
-  for (int q = 0; q < NL; ++q) {
-    const int idx = tid + q * NT;
-    if (idx < NPAIR) {
-      const int ly = idx / RXP;
-      const int o = ((ly & 1) << 1) * G::PLANE + (ly >> 1) * G::RXH + (idx - ly * RXP);
-      pl[o] = lv[q].x;
-      pl[o + G::PLANE] = lv[q].y;
-    }
-  }
-  __syncthreads();
-  T pv[4][K];
+}
+
+// The owned nodes' psi from the LDS planes; RING refreshes only the nodes
+// outside the tile.
+template <typename T, int TX, int TY, int S, int NT, int HX, bool RING>
+__device__ __forceinline__ void lds_to_regs(const T* pl, int lane, int b0,
+                                            T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K]) {
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
+    for (int r = 0; r < G::K; ++r) {
+      const int lx = 2 * lane + (c & 1), ly = 2 * (b0 + r) + (c >> 1);
       const bool in = lane < G::RXH && b0 + r < G::RYH;
-      pv[c][r] = in ? pl[c * G::PLANE + (b0 + r) * G::RXH + lane] : T(0);
+      const bool inner = lx >= G::H && lx < G::H + TX && ly >= G::H && ly < G::H + TY;
+      if (!RING) {
+        pv[c][r] = in ? pl[c * G::PLANE + (b0 + r) * G::RXH + lane] : T(0);
+      } else if (in && !inner) {
+        pv[c][r] = pl[c * G::PLANE + (b0 + r) * G::RXH + lane];
+      }
     }
   }
+}
 
-  const int lxd0 = 1 - x0, lxd1 = n - 2 - x0;  // domain interior in local coordinates
-  const int lyd0 = 1 - y0, lyd1 = n - 2 - y0;
+// S sweeps = 4S colour passes over the region.
+template <typename T, int TX, int TY, int S, int NT, int HX>
+__device__ __forceinline__ void tile_sweeps(T* pl, T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
+                                            const T (&fv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
+                                            int lxd0, int lxd1, int lyd0, int lyd1, int lane,
+                                            int b0, T w) {
 #pragma unroll 1
   for (int s = 0; s < S; ++s) {
     const int k = 4 * s;
@@ -404,15 +442,20 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
     colour_pass<T, TX, TY, S, NT, HX, 2>(pl, pv, fv, k + 3, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
     colour_pass<T, TX, TY, S, NT, HX, 3>(pl, pv, fv, k + 4, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
   }
+}
 
-  // Write the owned tile nodes, a pair (x even, x odd) per store where both
-  // are interior nodes; with CHECK also the tile's residual max |g - psi| and
-  // max |psi|.
-  double rmax = 0.0, pmax = 0.0;
+// Write the owned tile nodes, a pair (x even, x odd) per store where both
+// are interior nodes of the domain.
+template <typename T, int TX, int TY, int S, int NT, int HX, bool COHERENT = false>
+__device__ __forceinline__ void tile_to_global(T* __restrict__ pout, int n, int pitch, int x0,
+                                               int y0, int lane, int b0,
+                                               const T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K]) {
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
+  using T2 = typename Pair<T>::type;
 #pragma unroll
   for (int cy = 0; cy < 2; ++cy) {
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
+    for (int r = 0; r < G::K; ++r) {
       const int b = b0 + r;
       const int lx = 2 * lane, ly = 2 * b + cy;
       // both nodes of the pair are in the tile or neither (H and TX even)
@@ -423,7 +466,10 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
       const bool in0 = gx >= 1 && gx <= n - 2;
       const bool in1 = gx + 1 <= n - 2;  // gx + 1 >= 1 always
       const size_t g = (size_t)gy * pitch + gx;
-      if (in0 && in1) {
+      if (COHERENT) {
+        if (in0) coh_store(pout + g, pv[2 * cy][r]);
+        if (in1) coh_store(pout + g + 1, pv[2 * cy + 1][r]);
+      } else if (in0 && in1) {
         T2 v;
         v.x = pv[2 * cy][r];
         v.y = pv[2 * cy + 1][r];
@@ -435,13 +481,58 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
       }
     }
   }
-  if (CHECK) {
-    residual_pass<T, TX, TY, S, NT, HX, 0>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
-    residual_pass<T, TX, TY, S, NT, HX, 1>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
-    residual_pass<T, TX, TY, S, NT, HX, 2>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
-    residual_pass<T, TX, TY, S, NT, HX, 3>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
-  }
-  if (CHECK) block_max2<NT>(rmax, pmax);
+}
+
+// Residual max |g - psi| and max |psi| over the tile (valid in thread 0).
+template <typename T, int TX, int TY, int S, int NT, int HX>
+__device__ __forceinline__ void tile_residual(const T* pl,
+                                              const T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
+                                              const T (&fv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
+                                              int lxd0, int lxd1, int lyd0, int lyd1, int lane,
+                                              int b0, double& rmax, double& pmax) {
+  rmax = 0.0;
+  pmax = 0.0;
+  residual_pass<T, TX, TY, S, NT, HX, 0>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
+  residual_pass<T, TX, TY, S, NT, HX, 1>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
+  residual_pass<T, TX, TY, S, NT, HX, 2>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
+  residual_pass<T, TX, TY, S, NT, HX, 3>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
+  block_max2<NT>(rmax, pmax);
+}
+
+// One tile of S sweeps, shared by the per-launch kernel and the persistent
+// batched kernel.  sp is the block's LDS.  With CHECK the block-wide maxima
+// of |g - psi| and |psi| over the tile are returned in thread 0's rmax / pmax.
+template <typename T, int TX, int TY, int S, int NT, int HX>
+__device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restrict__ pout,
+                                         const T* __restrict__ F, int n, int pitch, int tile,
+                                         int tiles_x, T w, T* sp, bool CHECK, double& rmax_out,
+                                         double& pmax_out) {
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
+  constexpr int K = G::K;
+  T* const pl = sp + G::BASE;  // first parity plane
+  const int tyi = tile / tiles_x;
+  const int txi = tile - tyi * tiles_x;
+  const int x0 = txi * TX - G::H;  // region origin, even
+  const int y0 = tyi * TY - G::H;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  // the wavefront index is uniform: keeping it in a scalar register makes the
+  // per-row range tests of the colour passes scalar branches
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int b0 = wave * K;         // first owned row of every plane
+  T fv[4][K];
+  T pv[4][K];
+  region_to_lds<T, TX, TY, S, NT, HX, false>(pin, n, pitch, x0, y0, pl, tid);
+  rhs_to_regs<T, TX, TY, S, NT, HX>(F, n, pitch, x0, y0, lane, b0, fv);
+  __syncthreads();
+  lds_to_regs<T, TX, TY, S, NT, HX, false>(pl, lane, b0, pv);
+  const int lxd0 = 1 - x0, lxd1 = n - 2 - x0;  // domain interior in local coordinates
+  const int lyd0 = 1 - y0, lyd1 = n - 2 - y0;
+  tile_sweeps<T, TX, TY, S, NT, HX>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+  tile_to_global<T, TX, TY, S, NT, HX>(pout, n, pitch, x0, y0, lane, b0, pv);
+  double rmax = 0.0, pmax = 0.0;
+  if (CHECK)
+    tile_residual<T, TX, TY, S, NT, HX>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
   rmax_out = rmax;
   pmax_out = pmax;
 }
@@ -511,6 +602,7 @@ __device__ inline int load_state(const PoissonCtl* c) {
 __device__ bool grid_sync(BatchCtl* bc, unsigned int* flags, unsigned int nb, unsigned int& gen,
                           long long spin_ticks) {
   __shared__ int s_ok;
+  wait_vm();  // this wavefront's stores have reached L2 before block 0's release
   __syncthreads();
   gen += 1u;
   if (threadIdx.x == 0) {
@@ -731,6 +823,202 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
 }
 
 // ---------------------------------------------------------------------------
+// Resident FP64 solve: one launch per Poisson solve, one block per tile for
+// the whole solve.  A block keeps its tile's psi in LDS and the psi and F of
+// the nodes it owns in registers, so a round of S sweeps only reloads the
+// halo ring: the neighbours' tiles of the previous round, published through
+// the ping-pong pair (round r writes buffer (r + 1) % 2).  A block starts
+// round r once its (up to eight) neighbours have published round r - 1;
+// since a block publishes only after reading, two buffers suffice.  At the
+// start of every P-th round each block evaluates the residual of the state
+// after the previous round (its tile and the freshly loaded first ring are
+// exact) and leaves its maxima; one round later block 0 waits for every
+// block, reduces them and decides; one round after that every block applies
+// the decision.  The solve thus stops two rounds after the check that ended
+// it, the same in every block.
+//
+// Everything exchanged between blocks (tiles, flags, maxima, decisions) is
+// stored and loaded with device-scope 8-byte accesses; a block publishes a
+// round by waiting for its own stores (s_waitcnt in every wavefront) and
+// then storing its flag, so no block writes back or invalidates an L2 cache.
+// Waits poll with relaxed loads and are bounded by the wall clock: a grid
+// that is not co-resident ends with werror instead of hanging.
+// ---------------------------------------------------------------------------
+__device__ inline bool resident_failed(const ResidentCtl* rc, long long t0, long long spin) {
+  return coh_load(&rc->error) != 0 || wall_clock64() - t0 > spin;
+}
+__device__ inline void resident_fail(ResidentCtl* rc, PoissonCtl* ctl) {
+  coh_store(&rc->error, 1);
+  coh_store(&ctl->werror, 1);
+}
+
+template <int TX, int TY, int S, int NT>
+__global__ __launch_bounds__(NT) void k_sor_resident(double* __restrict__ bufa,
+                                                     double* __restrict__ bufb,
+                                                     const double* __restrict__ F, int n,
+                                                     int pitch, int tiles_x, int tiles_y,
+                                                     PoissonCtl* __restrict__ ctl,
+                                                     double* __restrict__ part,
+                                                     unsigned int* __restrict__ flags,
+                                                     ResidentCtl* __restrict__ rc, int P,
+                                                     long long spin_ticks) {
+  using G = SorGeom<double, TX, TY, S, NT, 0>;
+  constexpr int K = G::K;
+  __shared__ double sp[G::SLOTS];
+  __shared__ int s_go;
+  __shared__ double s_w;
+  // No block writes the control block before every block has published a
+  // round, so every block reads the same starting state here.
+  if (ctl->state != SOLVE_RUN) return;
+  double* const pl = sp + G::BASE;
+  const int ntiles = tiles_x * tiles_y;
+  int tile = blockIdx.x;
+  if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+  const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
+  const int x0 = txi * TX - G::H, y0 = tyi * TY - G::H;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int b0 = wave * K;
+  const int lxd0 = 1 - x0, lxd1 = n - 2 - x0, lyd0 = 1 - y0, lyd1 = n - 2 - y0;
+  // thread t < 9 (t != 4) watches neighbour t of the 3 x 3 tiles around this one
+  int nbr = -1;
+  if (tid < 9 && tid != 4) {
+    const int nx = txi + tid % 3 - 1, ny = tyi + tid / 3 - 1;
+    if (nx >= 0 && nx < tiles_x && ny >= 0 && ny < tiles_y) nbr = ny * tiles_x + nx;
+  }
+  double fv[4][K], pv[4][K];
+  double w = ctl->relax;
+  region_to_lds<double, TX, TY, S, NT, 0, false>(bufa, n, pitch, x0, y0, pl, tid);
+  rhs_to_regs<double, TX, TY, S, NT, 0>(F, n, pitch, x0, y0, lane, b0, fv);
+  __syncthreads();
+  lds_to_regs<double, TX, TY, S, NT, 0, false>(pl, lane, b0, pv);
+  int r = 0;
+  bool stopped = false;
+  for (;; ++r) {
+    // Values the round's addresses derive from, re-materialised every round:
+    // without this the compiler hoists every per-thread address of the ring
+    // load, the refresh and the store out of the loop and runs out of
+    // registers.
+    int tid_r = tid, lane_r = lane;
+    asm volatile("" : "+v"(tid_r), "+v"(lane_r));
+    if (r > 0) {
+      // the neighbours have published round r - 1
+      int ok = 1;
+      if (nbr >= 0) {
+        const long long t0 = wall_clock64();
+        while (coh_load(&flags[nbr * kFlagStride]) < (unsigned int)r) {
+          __builtin_amdgcn_s_sleep(1);
+          if (resident_failed(rc, t0, spin_ticks)) {
+            ok = 0;
+            break;
+          }
+        }
+      }
+      if (!__syncthreads_and(ok)) {
+        if (tid == 0) resident_fail(rc, ctl);
+        break;
+      }
+      region_to_lds<double, TX, TY, S, NT, 0, true, 2, true>((r & 1) ? bufb : bufa, n, pitch, x0,
+                                                            y0, pl, tid_r);
+      __syncthreads();
+      lds_to_regs<double, TX, TY, S, NT, 0, true>(pl, lane_r, b0, pv);
+      // residual of the state after round r - 1 (check c = r / P - 1)
+      if (r % P == 0) {
+        double rm, pm;
+        tile_residual<double, TX, TY, S, NT, 0>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane_r, b0,
+                                                rm, pm);
+        if (tid == 0) {
+          const int slot = (r / P - 1) & 1;
+          coh_store(&part[2 * (slot * ntiles + tile)], rm);
+          coh_store(&part[2 * (slot * ntiles + tile) + 1], pm);
+        }
+      }
+      // block 0 decides check c = (r - 1) / P - 1 once every block has
+      // published the round that evaluated it
+      if (blockIdx.x == 0 && r % P == 1 && r > P) {
+        const int slot = ((r - 1) / P - 1) & 1;
+        int ok2 = 1;
+        const long long t0 = wall_clock64();
+        for (int b = tid; b < ntiles && ok2; b += NT) {
+          while (coh_load(&flags[b * kFlagStride]) < (unsigned int)r) {
+            __builtin_amdgcn_s_sleep(1);
+            if (resident_failed(rc, t0, spin_ticks)) {
+              ok2 = 0;
+              break;
+            }
+          }
+        }
+        if (!__syncthreads_and(ok2)) {
+          if (tid == 0) resident_fail(rc, ctl);
+          break;
+        }
+        double rr = 0.0, pp = 0.0;
+        for (int q = tid; q < ntiles; q += NT) {
+          rr = fmax(rr, coh_load(&part[2 * (slot * ntiles + q)]));
+          pp = fmax(pp, coh_load(&part[2 * (slot * ntiles + q) + 1]));
+        }
+        block_max2<NT>(rr, pp);
+        if (tid == 0) {
+          decide(ctl, rr, pp, ctl->sweeps_per_check);
+          coh_store(&rc->state[slot], ctl->state);
+          coh_store(&rc->relax[slot], ctl->relax);
+          wait_vm();
+          coh_store(&rc->tag[slot], (unsigned int)((r - 1) / P));
+        }
+      }
+      // every block applies decision c = (r - 2) / P - 1
+      if (r % P == 2 && r > P + 1) {
+        const unsigned int want = (unsigned int)((r - 2) / P);
+        const int slot = (int)(want - 1) & 1;
+        if (tid == 0) {
+          int ok3 = 1;
+          const long long t0 = wall_clock64();
+          while (coh_load(&rc->tag[slot]) != want) {
+            __builtin_amdgcn_s_sleep(1);
+            if (resident_failed(rc, t0, spin_ticks)) {
+              ok3 = 0;
+              break;
+            }
+          }
+          if (ok3) {
+            s_go = coh_load(&rc->state[slot]) == SOLVE_RUN ? 1 : 0;
+            s_w = coh_load(&rc->relax[slot]);
+          } else {
+            resident_fail(rc, ctl);
+            s_go = -1;
+          }
+        }
+        __syncthreads();
+        const int go = s_go;
+        w = s_w;
+        __syncthreads();
+        if (go < 0) break;
+        if (go == 0) {
+          stopped = true;
+          break;
+        }
+      }
+    }
+    tile_sweeps<double, TX, TY, S, NT, 0>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane_r, b0, w);
+    tile_to_global<double, TX, TY, S, NT, 0, true>((r & 1) ? bufa : bufb, n, pitch, x0, y0,
+                                                   lane_r, b0, pv);
+    wait_vm();
+    __syncthreads();
+    if (tid == 0) coh_store(&flags[tile * kFlagStride], (unsigned int)(r + 1));
+  }
+  if (!stopped) return;
+  // Rounds 0 .. r - 1 are done and the last one sits in buffer r % 2; the
+  // result belongs in psi.  The decision counted the sweeps up to its check,
+  // two rounds before the stop.
+  if (r & 1) tile_to_global<double, TX, TY, S, NT, 0>(bufa, n, pitch, x0, y0, lane, b0, pv);
+  if (blockIdx.x == 0 && tid == 0) {
+    ctl->sweeps += 2LL * S;
+    ctl->total_sweeps += 2LL * S;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
 // Geometric multigrid for the compact stream equation (coarse levels are the
 // same compact operator rediscretised on a coarser grid).  A level with m
 // intervals (h = 1/m) coarsens to ceil(m/2) intervals; for odd m the grids
@@ -946,6 +1234,7 @@ __global__ void k_ctl_reset(PoissonCtl* c, double relax, double tol_hat, long lo
   c->stall_window = stall_window;
   c->sweeps_per_check = sweeps_per_check;
   c->floor_limited = 0;
+  c->werror = 0;
 }
 
 // r = g(psi) - psi in FP64 on interior nodes, reduced to max |r| for the solve
@@ -1279,6 +1568,8 @@ bool sor_config_supported(const SorConfig& c, bool fp32) {
 
 int sor_max_blocks(int n) { return ((n + 31) / 32) * ((n + 31) / 32); }
 
+
+
 #define CAV_BATCH_CONFIGS_F64(X) \
   X(32, 32, 1, 256)              \
   X(64, 32, 2, 512)              \
@@ -1502,6 +1793,55 @@ hipError_t launch_copy_interior(const double* src, double* dst, int n, int pitch
                                 hipStream_t st) {
   hipLaunchKernelGGL(k_copy, grid2d(n, n), dim3(kBlock), 0, st, src, dst, n, pitch, 3);
   return hipGetLastError();
+}
+
+
+// Tile shapes of the resident solve.
+#define CAV_RESIDENT_CONFIGS(X) \
+  X(64, 64, 4, 768)             \
+  X(32, 32, 2, 256)
+
+size_t resident_flag_bytes(int n) {
+  return (size_t)sor_max_blocks(n) * kFlagStride * sizeof(unsigned int);
+}
+
+namespace {
+template <int TX, int TY, int S, int NT>
+int resident_capacity(int device) {
+  return occupancy_grid(k_sor_resident<TX, TY, S, NT>, NT, device);
+}
+}  // namespace
+
+bool resident_supported(const SorConfig& c, int n, int device) {
+#define CAV_RES_FITS(TX_, TY_, S_, NT_)                                                \
+  if (c.tx == TX_ && c.ty == TY_ && c.s == S_ && c.nt == NT_)                          \
+    return ((n + TX_ - 1) / TX_) * ((n + TY_ - 1) / TY_) <=                            \
+           resident_capacity<TX_, TY_, S_, NT_>(device);
+  CAV_RESIDENT_CONFIGS(CAV_RES_FITS)
+#undef CAV_RES_FITS
+  return false;
+}
+
+hipError_t launch_sor64_resident(const SorConfig& c, double* psi, double* psi_b, const double* F,
+                                 int n, int pitch, PoissonCtl* ctl, double* part,
+                                 unsigned int* flags, ResidentCtl* rctl, int rounds_per_check,
+                                 long long spin_ticks, int device, hipStream_t st) {
+  if (!resident_supported(c, n, device) || rounds_per_check < 3)
+    return hipErrorInvalidConfiguration;
+  hipError_t e = launch_zero(flags, resident_flag_bytes(n), st);
+  if (e != hipSuccess) return e;
+  if ((e = launch_zero(rctl, sizeof(ResidentCtl), st)) != hipSuccess) return e;
+#define CAV_RES_LAUNCH(TX_, TY_, S_, NT_)                                                    \
+  if (c.tx == TX_ && c.ty == TY_ && c.s == S_ && c.nt == NT_) {                            \
+    const int tx = (n + TX_ - 1) / TX_, ty = (n + TY_ - 1) / TY_;                          \
+    hipLaunchKernelGGL((k_sor_resident<TX_, TY_, S_, NT_>), dim3(tx * ty), dim3(NT_), 0, st, \
+                       psi, psi_b, F, n, pitch, tx, ty, ctl, part, flags, rctl,            \
+                       rounds_per_check, spin_ticks);                                      \
+    return hipGetLastError();                                                              \
+  }
+  CAV_RESIDENT_CONFIGS(CAV_RES_LAUNCH)
+#undef CAV_RES_LAUNCH
+  return hipErrorInvalidConfiguration;
 }
 
 }  // namespace cav

@@ -102,6 +102,8 @@ struct Member {
   float* psi32 = nullptr;      // mixed: FP32 shadow of psi for the transport stencil
   cav::PoissonCtl* ctl = nullptr;
   double* part = nullptr;      // per-block partial maxima of a residual check
+  unsigned int* rflags = nullptr;     // resident solve: per-tile round flags
+  cav::ResidentCtl* rctl = nullptr;   // resident solve: decision exchange
   double* diag_partial = nullptr;
   double* diag_out = nullptr;
   int diag_np = 0;
@@ -248,7 +250,9 @@ int derive(const cavity_params& p, Member& m) {
 }
 
 size_t part_doubles(int n) {
-  return 2 * (size_t)std::max(cav::sor_max_blocks(n), cav::resid_blocks());
+  // two maxima per block of a checking launch or of the residual kernel;
+  // a resident solve keeps two check slots of two maxima per tile
+  return 4 * (size_t)std::max(cav::sor_max_blocks(n), cav::resid_blocks());
 }
 
 size_t flag_bytes() { return (size_t)cav::kMaxBatchGrid * cav::kFlagStride * sizeof(unsigned int); }
@@ -287,6 +291,7 @@ size_t member_bytes(const Member& m) {
   if (m.mixed) b += 4 * f32;
   b += align_up(sizeof(cav::PoissonCtl));
   b += align_up(part_doubles(m.n) * sizeof(double));
+  b += align_up(cav::resident_flag_bytes(m.n)) + align_up(sizeof(cav::ResidentCtl));
   b += align_up((size_t)cav::diag_partials(m.n) * 4 * sizeof(double));
   b += align_up(4 * sizeof(double));
   b += mg_bytes(m.n);
@@ -315,6 +320,8 @@ void carve(Member& m, char*& cur) {
   }
   m.ctl = reinterpret_cast<cav::PoissonCtl*>(take(align_up(sizeof(cav::PoissonCtl))));
   m.part = reinterpret_cast<double*>(take(align_up(part_doubles(m.n) * sizeof(double))));
+  m.rflags = reinterpret_cast<unsigned int*>(take(align_up(cav::resident_flag_bytes(m.n))));
+  m.rctl = reinterpret_cast<cav::ResidentCtl*>(take(align_up(sizeof(cav::ResidentCtl))));
   m.diag_np = cav::diag_partials(m.n);
   m.diag_partial = reinterpret_cast<double*>(take(align_up((size_t)m.diag_np * 4 * 8)));
   m.diag_out = reinterpret_cast<double*>(take(align_up(4 * sizeof(double))));
@@ -525,16 +532,60 @@ int read_ctls(cavity_s* h, const std::vector<int>& idx) {
   return CAVITY_OK;
 }
 
+// Tile shape of a resident solve for member m, if it has one on this device:
+// 64 x 64 tiles (768 threads) from n > 512, 32 x 32 below, as long as every
+// tile gets a co-resident block.
+bool resident_config(const cavity_s* h, const Member& m, cav::SorConfig* c) {
+  if (h->exec != CAVITY_EXEC_RESIDENT || m.mixed || m.solver != CAVITY_SOLVER_SOR || m.fixed)
+    return false;
+  const cav::SorConfig big{64, 64, 4, 768, 0}, small{32, 32, 2, 256, 0};
+  if (m.n > 512 && cav::resident_supported(big, m.n, h->device)) {
+    *c = big;
+    return true;
+  }
+  if (cav::resident_supported(small, m.n, h->device)) {
+    *c = small;
+    return true;
+  }
+  return false;
+}
+
+// One resident launch for the whole solve of m (after its control reset and
+// initial check).  Rounds per check follow the member's check spacing, but
+// at least half the tile grid's width plus one, so that no block can run
+// far enough ahead to reuse a partial-maximum slot block 0 is still reading.
+int enqueue_resident(cavity_s* h, Member& m, const cav::SorConfig& c) {
+  const int tiles = std::max((m.n + c.tx - 1) / c.tx, (m.n + c.ty - 1) / c.ty);
+  const long long spc = 2LL * m.cfg64.s * m.pairs_per_check;
+  const int P = std::max<int>({3, tiles / 2 + 1, (int)((spc + c.s - 1) / c.s)});
+  const double tol_hat = m.tol * 0.3 * m.h * m.h;
+  HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, m.stall_window,
+                                   (long long)P * c.s, h->st));
+  HIP_TRY(h, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, m.part,
+                                 h->st));
+  const long long spin = 10LL * 100000000LL;  // 10 s of the 100 MHz wall clock
+  HIP_TRY(h, cav::launch_sor64_resident(c, m.psi, m.psi_b, m.F, m.n, m.pitch, m.ctl, m.part,
+                                        m.rflags, m.rctl, P, spin, h->device, h->st));
+  return CAVITY_OK;
+}
+
 // state_solve: the solve produces the state's psi (refresh its FP32 shadow);
 // false for solves into scratch buffers.
 int solve_members(cavity_s* h, const std::vector<int>& idx, bool state_solve = true) {
   int rc;
+  std::vector<int> active, resident;
   for (int k : idx) {
     Member& m = h->m[k];
+    cav::SorConfig rcfg;
+    if (resident_config(h, m, &rcfg)) {
+      if ((rc = enqueue_resident(h, m, rcfg)) != CAVITY_OK) return rc;
+      resident.push_back(k);
+      continue;
+    }
     if ((rc = reset_ctl(h, m)) != CAVITY_OK) return rc;
     if ((rc = enqueue_initial_check(h, m)) != CAVITY_OK) return rc;
+    active.push_back(k);
   }
-  std::vector<int> active = idx;
   std::vector<long long> enqueued(h->count, 0);
   bool first = true;
   while (!active.empty()) {
@@ -569,6 +620,14 @@ int solve_members(cavity_s* h, const std::vector<int>& idx, bool state_solve = t
       still.push_back(k);
     }
     active.swap(still);
+  }
+  if (!resident.empty() && (rc = read_ctls(h, resident)) != CAVITY_OK) return rc;
+  for (int k : resident) {
+    if (h->host_ctl[k].werror) {
+      h->poisoned = true;
+      return fail(CAVITY_EHIP, "resident solve of cavity %d: a wait timed out (tiles not "
+                               "co-resident?)", k);
+    }
   }
   for (int k : idx) {
     Member& m = h->m[k];
@@ -893,7 +952,7 @@ int step_all(cavity_s* h, bool want_diag) {
     m.status_step = CAVITY_OK;
     if (want_diag) HIP_TRY(h, cav::launch_copy(m.psi, m.psi_prev, m.n, m.pitch, h->st));
   }
-  if (h->exec == CAVITY_EXEC_STREAM) {
+  if (h->exec == CAVITY_EXEC_STREAM || h->exec == CAVITY_EXEC_RESIDENT) {
     std::vector<int> solved, fixed;
     for (int k = 0; k < h->count; ++k) (h->m[k].fixed > 0 ? fixed : solved).push_back(k);
     for (int stage = 1; stage <= 5; ++stage) {
@@ -1689,10 +1748,13 @@ int cavity_get_exec(cavity_t h, int32_t* mode) {
 int cavity_set_exec(cavity_t h, int32_t mode) {
   if (!h) return fail(CAVITY_EINVAL, "null handle");
   if (h->poisoned) return fail(CAVITY_ESTATE, "handle poisoned by an earlier failure");
-  if (mode != CAVITY_EXEC_STREAM && mode != CAVITY_EXEC_PERSISTENT && mode != CAVITY_EXEC_GRAPH)
+  if (mode != CAVITY_EXEC_STREAM && mode != CAVITY_EXEC_PERSISTENT && mode != CAVITY_EXEC_GRAPH &&
+      mode != CAVITY_EXEC_RESIDENT)
     return fail(CAVITY_EINVAL, "unknown execution mode %d", mode);
   HIP_TRY(h, hipSetDevice(h->device));
-  if (mode == CAVITY_EXEC_GRAPH && all_fixed(h)) {
+  if (mode == CAVITY_EXEC_RESIDENT) {
+    // nothing to prepare: eligible solves launch resident, the rest stream
+  } else if (mode == CAVITY_EXEC_GRAPH && all_fixed(h)) {
     // coupled mode: the step has no decision to wait for, the graph holds
     // the per-launch kernels as they are
     const int rc = collect_totals(h, false);
