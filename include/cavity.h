@@ -223,9 +223,10 @@ int cavity_relax(cavity_t h, int32_t idx, int32_t sweeps, int32_t arith, double*
 
 /*
  * Launch configuration of a cavity's Poisson smoother.  The sweep kernel loads
- * a tile_x x tile_y tile of psi and of the right-hand side plus a halo into
- * LDS and runs sweeps_per_launch four-colour sweeps there; only compiled
- * combinations are accepted (EINVAL otherwise).  Results do not depend on the
+ * a tile_x x tile_y tile of psi plus a halo into LDS (and the right-hand side
+ * of the nodes each thread updates into registers) and runs
+ * sweeps_per_launch four-colour sweeps there; only compiled combinations are
+ * accepted (EINVAL otherwise).  Results do not depend on the
  * tile shape or thread count; sweeps_per_launch, check_every and sor_omega
  * change the sweep schedule and so the last bits of the converged result.
  */

@@ -502,7 +502,7 @@ __device__ __forceinline__ void tile_residual(const T* pl,
 // One tile of S sweeps, shared by the per-launch kernel and the persistent
 // batched kernel.  sp is the block's LDS.  With CHECK the block-wide maxima
 // of |g - psi| and |psi| over the tile are returned in thread 0's rmax / pmax.
-template <typename T, int TX, int TY, int S, int NT, int HX>
+template <typename T, int TX, int TY, int S, int NT, int HX, bool COH = false>
 __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restrict__ pout,
                                          const T* __restrict__ F, int n, int pitch, int tile,
                                          int tiles_x, T w, T* sp, bool CHECK, double& rmax_out,
@@ -522,14 +522,14 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
   const int b0 = wave * K;         // first owned row of every plane
   T fv[4][K];
   T pv[4][K];
-  region_to_lds<T, TX, TY, S, NT, HX, false>(pin, n, pitch, x0, y0, pl, tid);
+  region_to_lds<T, TX, TY, S, NT, HX, false, 0, COH>(pin, n, pitch, x0, y0, pl, tid);
   rhs_to_regs<T, TX, TY, S, NT, HX>(F, n, pitch, x0, y0, lane, b0, fv);
   __syncthreads();
   lds_to_regs<T, TX, TY, S, NT, HX, false>(pl, lane, b0, pv);
   const int lxd0 = 1 - x0, lxd1 = n - 2 - x0;  // domain interior in local coordinates
   const int lyd0 = 1 - y0, lyd1 = n - 2 - y0;
   tile_sweeps<T, TX, TY, S, NT, HX>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
-  tile_to_global<T, TX, TY, S, NT, HX>(pout, n, pitch, x0, y0, lane, b0, pv);
+  tile_to_global<T, TX, TY, S, NT, HX, COH>(pout, n, pitch, x0, y0, lane, b0, pv);
   double rmax = 0.0, pmax = 0.0;
   if (CHECK)
     tile_residual<T, TX, TY, S, NT, HX>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
@@ -653,6 +653,51 @@ __device__ bool grid_sync(BatchCtl* bc, unsigned int* flags, unsigned int nb, un
   return s_ok != 0;
 }
 
+// The same barrier for kernels whose cross-block data all move through
+// device-scope loads and stores: every wavefront waits for its own stores,
+// and no block writes back or invalidates an L2 cache.
+__device__ bool grid_sync_coh(BatchCtl* bc, unsigned int* flags, unsigned int nb,
+                              unsigned int& gen, long long spin_ticks) {
+  __shared__ int s_ok;
+  wait_vm();
+  __syncthreads();
+  gen += 1u;
+  if (threadIdx.x == 0) coh_store(&flags[blockIdx.x * kFlagStride], gen);
+  int ok = 1;
+  if (blockIdx.x == 0) {
+    const long long t0 = wall_clock64();
+    for (unsigned int b = threadIdx.x; b < nb && ok; b += blockDim.x) {
+      while (coh_load(&flags[b * kFlagStride]) != gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (coh_load(&bc->error) != 0 || wall_clock64() - t0 > spin_ticks) {
+          ok = 0;
+          break;
+        }
+      }
+    }
+    ok = __syncthreads_and(ok);
+    if (threadIdx.x == 0) {
+      if (ok)
+        coh_store(&bc->go, gen);
+      else
+        coh_store(&bc->error, 1);
+    }
+  } else if (threadIdx.x == 0) {
+    const long long t0 = wall_clock64();
+    while (coh_load(&bc->go) != gen) {
+      __builtin_amdgcn_s_sleep(1);
+      if (coh_load(&bc->error) != 0 || wall_clock64() - t0 > spin_ticks) {
+        coh_store(&bc->error, 1);
+        ok = 0;
+        break;
+      }
+    }
+  }
+  if (threadIdx.x == 0) s_ok = ok;
+  __syncthreads();
+  return s_ok != 0;
+}
+
 // The generation every block starts a launch with, and the record of the
 // one it ended with (block 0, after the last barrier every block passed).
 __device__ inline unsigned int batch_epoch(const BatchCtl* bc) {
@@ -691,12 +736,16 @@ __device__ void batch_decide(const BatchMember* mem, int count, long long sweeps
   if (load_state(m.ctl) != SOLVE_RUN) return;
   double r = 0.0, p = 0.0;
   for (int q = threadIdx.x; q < m.tiles; q += NT) {
-    r = fmax(r, m.part[2 * q]);
-    p = fmax(p, m.part[2 * q + 1]);
+    r = fmax(r, coh_load(&m.part[2 * q]));
+    p = fmax(p, coh_load(&m.part[2 * q + 1]));
   }
   block_max2<NT>(r, p);
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
     decide(m.ctl, r, p, sweeps_done < 0 ? m.ctl->sweeps_per_check : sweeps_done);
+    // what the other blocks read of the decision, device-coherent
+    coh_store(&m.ctl->state, m.ctl->state);
+    coh_store(&m.ctl->relax, m.ctl->relax);
+  }
 }
 
 template <int TX, int TY, int S, int NT>
@@ -717,24 +766,25 @@ __global__ __launch_bounds__(NT) void k_batch64(const BatchMember* __restrict__ 
         const BatchMember& m = mem[member_of(mem, count, t)];
         if (load_state(m.ctl) != SOLVE_RUN) continue;
         const int lt = t - m.tile0;
-        const double w = m.ctl->relax;
+        const double w = coh_load(&m.ctl->relax);
         const double* pin = fwd ? m.psi : m.psi_b;
         double* pout = fwd ? m.psi_b : m.psi;
         double rmax = 0.0, pmax = 0.0;
-        // one inlined tile body for both kinds of round keeps the register
-        // budget of 1024-thread blocks
-        sor_tile<double, TX, TY, S, NT, 2>(pin, pout, m.F, m.n, m.pitch, lt, m.tiles_x, w, sp,
-                                           check, rmax, pmax);
+        // one inlined tile body for both kinds of round; psi moves between
+        // blocks through device-scope loads and stores, so the barrier needs
+        // no cache write-back or invalidation
+        sor_tile<double, TX, TY, S, NT, 2, true>(pin, pout, m.F, m.n, m.pitch, lt, m.tiles_x, w,
+                                                 sp, check, rmax, pmax);
         if (check && threadIdx.x == 0) {
-          m.part[2 * lt] = rmax;
-          m.part[2 * lt + 1] = pmax;
+          coh_store(&m.part[2 * lt], rmax);
+          coh_store(&m.part[2 * lt + 1], pmax);
         }
         __syncthreads();
       }
-      if (!grid_sync(bc, flags, nb, gen, spin_ticks)) return;
+      if (!grid_sync_coh(bc, flags, nb, gen, spin_ticks)) return;
     }
     batch_decide<NT>(mem, count, -1);
-    if (!grid_sync(bc, flags, nb, gen, spin_ticks)) return;
+    if (!grid_sync_coh(bc, flags, nb, gen, spin_ticks)) return;
   }
   batch_end(bc, gen);
 }
