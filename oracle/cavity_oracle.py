@@ -317,7 +317,8 @@ def sor_lexicographic(omega: np.ndarray, beta: float, psi0: np.ndarray | None = 
     return np.array(P), max_sweeps
 
 
-def sor_four_colour_sweep(psi: np.ndarray, omega: np.ndarray, relax: float) -> np.ndarray:
+def sor_four_colour_sweep(psi: np.ndarray, omega: np.ndarray, relax: float,
+                          h: float | None = None) -> np.ndarray:
     """One relaxation sweep of eq. (SequationFinal) in four-colour order.
 
     The paper visits nodes lexicographically; a parallel machine cannot.  In
@@ -327,16 +328,22 @@ def sor_four_colour_sweep(psi: np.ndarray, omega: np.ndarray, relax: float) -> n
     by the groups before it.  Within one group every node receives the
     update of eq. (SequationFinal) with relaxation parameter ``relax``.  The
     fixed point is the same linear system's solution.  Returns a new array.
+
+    ``h`` defaults to the spacing of an n x n grid of the unit square; giving
+    it lets the sweep run on a window cut from a larger grid (the window's
+    edge nodes are held fixed, and its origin must have even indices so that
+    the colours are the global ones).
     """
-    n = psi.shape[0]
-    h = mesh_spacing(n)
+    ny, nx = psi.shape
+    if h is None:
+        h = mesh_spacing(nx)
     b = c = 1.0 / (h * h)
     a = b + c
     p = np.array(psi, dtype=np.float64, copy=True)
-    Bv = np.zeros((n, n))
+    Bv = np.zeros((ny, nx))
     Bv[1:-1, 1:-1] = poisson_rhs(omega)
-    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
-    inner = (ii > 0) & (ii < n - 1) & (jj > 0) & (jj < n - 1)
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    inner = (ii > 0) & (ii < nx - 1) & (jj > 0) & (jj < ny - 1)
     for (pi, pj) in ((0, 0), (1, 0), (0, 1), (1, 1)):
         m = inner & (ii % 2 == pi) & (jj % 2 == pj)
         js, is_ = np.nonzero(m)

@@ -94,21 +94,23 @@ def test_four_colour_relaxation_converges_to_same_solution():
     assert np.max(np.abs(psi - got)) <= 1e-12 * np.max(np.abs(got))
 
 
-def test_four_colour_sweep_is_pointwise_relaxation_in_colour_order():
-    """Brute force: loop node by node over the four groups, updating in place."""
-    n = 9
-    h = mesh_spacing(n)
+@pytest.mark.parametrize("ny,nx,hgiven", [(9, 9, None), (7, 12, 0.05)])
+def test_four_colour_sweep_is_pointwise_relaxation_in_colour_order(ny, nx, hgiven):
+    """Brute force: loop node by node over the four groups, updating in place
+    (also on a rectangular window with a given spacing)."""
+    h = mesh_spacing(nx) if hgiven is None else hgiven
     b = c = 1.0 / h**2
     a = b + c
     rng = np.random.default_rng(11)
-    omega = rng.standard_normal((n, n))
-    psi0 = rng.standard_normal((n, n))
-    psi0[0, :] = psi0[-1, :] = psi0[:, 0] = psi0[:, -1] = 0.0
+    omega = rng.standard_normal((ny, nx))
+    psi0 = rng.standard_normal((ny, nx))
+    if hgiven is None:
+        psi0[0, :] = psi0[-1, :] = psi0[:, 0] = psi0[:, -1] = 0.0
     beta = 1.7
     P = psi0.copy()
     for (pi, pj) in ((0, 0), (1, 0), (0, 1), (1, 1)):
-        for j in range(1, n - 1):
-            for i in range(1, n - 1):
+        for j in range(1, ny - 1):
+            for i in range(1, nx - 1):
                 if i % 2 != pi or j % 2 != pj:
                     continue
                 A = b * (P[j, i + 1] + P[j, i - 1]) + c * (P[j + 1, i] + P[j - 1, i])
@@ -118,8 +120,36 @@ def test_four_colour_sweep_is_pointwise_relaxation_in_colour_order():
                               - 2 * P[j, i + 1] - 2 * P[j, i - 1]
                               + P[j - 1, i + 1] - 2 * P[j - 1, i] + P[j - 1, i - 1])
                 P[j, i] = 3 / 5 * beta / a * (A + B + C) + (1 - beta) * P[j, i]
-    got = sor_four_colour_sweep(psi0, omega, beta)
+    got = sor_four_colour_sweep(psi0, omega, beta, h=hgiven)
     assert np.max(np.abs(got - P)) <= 1e-13 * np.max(np.abs(P))
+
+
+def test_windowed_sweeps_reproduce_full_grid_sweeps():
+    """After k sweeps a node depends only on nodes within 4k of it (each of
+    the four colour passes reaches one node further).  Sweeps on an
+    even-aligned window with the full grid's spacing then give the full
+    grid's values at the sample node; a window four nodes short of that reach
+    does not, by far more than the tolerance (the reach is not overstated
+    by much, so the check has teeth)."""
+    n, k, beta = 121, 5, 1.7
+    rng = np.random.default_rng(17)
+    omega = rng.standard_normal((n, n))
+    full = np.zeros((n, n))
+    for _ in range(k):
+        full = sor_four_colour_sweep(full, omega, beta)
+    h = mesh_spacing(n)
+
+    def windowed(j, i, rad):
+        j0, i0 = max(0, (j - rad) // 2 * 2), max(0, (i - rad) // 2 * 2)
+        j1, i1 = min(n, j + rad + 1), min(n, i + rad + 1)
+        win = np.zeros((j1 - j0, i1 - i0))
+        for _ in range(k):
+            win = sor_four_colour_sweep(win, omega[j0:j1, i0:i1], beta, h=h)
+        return win[j - j0, i - i0]
+
+    for (j, i) in ((60, 60), (40, 2), (n - 3, n - 3), (1, 77)):
+        assert abs(windowed(j, i, 4 * k + 4) - full[j, i]) <= 1e-13 * np.max(np.abs(full))
+    assert abs(windowed(61, 61, 4 * k - 4) - full[61, 61]) > 1e-11 * np.max(np.abs(full))
 
 
 def _poly_case(n, which):
