@@ -547,9 +547,15 @@ __global__ __launch_bounds__(NT) void k_sor(const T* __restrict__ pin, T* __rest
   __shared__ T sp[G::SLOTS];
   if (ctl->state != SOLVE_RUN) return;
   const T w = (T)(relax_arg > 0.0 ? relax_arg : ctl->relax);
+  // XCD bands: blocks are dealt to the eight XCDs in turn (block b to XCD
+  // b mod 8), so XCD x gets a contiguous band of tiles, nb / 8 of them plus
+  // one for the first nb mod 8 XCDs; neighbouring tiles then share an L2.
   const int nb = gridDim.x;
   int tile = blockIdx.x;
-  if (xcd_bands && (nb & 7) == 0) tile = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  if (xcd_bands) {
+    const int q = nb >> 3, r = nb & 7, x = blockIdx.x & 7;
+    tile = x * q + min(x, r) + (blockIdx.x >> 3);
+  }
   double rmax = 0.0, pmax = 0.0;
   sor_tile<T, TX, TY, S, NT, HX>(pin, pout, F, n, pitch, tile, tiles_x, w, sp, CHECK, rmax,
                                  pmax);
@@ -1518,7 +1524,9 @@ hipError_t sor_launch(const T* pin, T* pout, const T* F, int n, int pitch, Poiss
   X(64, 64, 4, 1024)           \
   X(64, 64, 4, 768)            \
   X(96, 64, 2, 1024)           \
-  X(96, 64, 3, 1024)
+  X(96, 64, 3, 1024)           \
+  X(92, 50, 4, 1024)           \
+  X(84, 54, 5, 1024)
 
 #define CAV_SOR_CONFIGS_F32(X) \
   X(32, 32, 1, 256)            \

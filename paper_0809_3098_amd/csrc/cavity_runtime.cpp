@@ -225,22 +225,23 @@ int derive(const cavity_params& p, Member& m) {
   // A stalled over-relaxation sits at its rounding floor; allow several
   // residual halvings' worth of sweeps (about 0.11 (n-1) each) before polishing.
   m.stall_window = std::max<long long>(64, 2LL * p.n);
-  // tiles: small grids favour more, smaller blocks.  Measured on MI355X:
-  // at 1024^2, 64 x 64 tiles with 4 (FP64) or 6 (FP32) sweeps per launch and
-  // 1024 threads; at 4096^2, 96 x 64 tiles with 3 sweeps per launch; the
-  // XCD-banded tile order helps while the tile count is a multiple of 8.
-  auto banded = [&](int tx, int ty) {
-    return (((p.n + tx - 1) / tx) * ((p.n + ty - 1) / ty)) % 8 == 0 ? 1 : 0;
-  };
+  // tiles: small grids favour more, smaller blocks.  A launch of 1024
+  // threads costs about a fixed part (start, region load, store) plus, per
+  // sweep, the plane rows each wavefront walks; a region row is at most 128
+  // nodes (64 per parity plane, one per lane).  Measured on MI355X: at
+  // 1024^2, 84 x 54 tiles with 5 sweeps per launch (FP64; 247 tiles, one per
+  // CU, three plane rows per wavefront, full 64-lane rows) take 3.5 us per
+  // sweep against 3.9 for 64 x 64 with 4; FP32 keeps 64 x 64 with 6.  At
+  // 4096^2, 96 x 64 tiles with 3 sweeps.  XCD-banded tile order throughout.
   if (p.n <= 320) {
     m.cfg64 = {32, 32, 1, 256, 0};
     m.cfg32 = {32, 32, 1, 256, 0};
   } else if (p.n <= 2048) {
-    m.cfg64 = {64, 64, 4, 1024, banded(64, 64)};
-    m.cfg32 = {64, 64, 6, 1024, banded(64, 64)};
+    m.cfg64 = {84, 54, 5, 1024, 1};
+    m.cfg32 = {64, 64, 6, 1024, 1};
   } else {
-    m.cfg64 = {96, 64, 3, 1024, banded(96, 64)};
-    m.cfg32 = {96, 64, 3, 1024, banded(96, 64)};
+    m.cfg64 = {96, 64, 3, 1024, 1};
+    m.cfg32 = {96, 64, 3, 1024, 1};
   }
   // Residual checks every n/16 sweeps (4 to 64): a solve needs O(n) sweeps,
   // so the overshoot past convergence stays a fixed small fraction while the
@@ -1645,7 +1646,8 @@ int cavity_autotune(cavity_t h, int32_t idx, const char* cache_path, cavity_tuni
                              {64, 64, 1, 1024, 0}, {64, 64, 2, 1024, 0}, {64, 64, 3, 1024, 0},
                              {64, 64, 2, 512, 0},  {64, 64, 4, 512, 0},  {64, 64, 4, 1024, 0},
                              {96, 64, 2, 1024, 0},
-                             {96, 64, 3, 1024, 0}};
+                             {96, 64, 3, 1024, 0}, {92, 50, 4, 1024, 0},
+                             {84, 54, 5, 1024, 0}};
   static const std::vector<Cand> k32 = {{32, 32, 1, 256, 0}, {32, 32, 2, 256, 0}, {64, 32, 2, 512, 0},
                              {64, 64, 2, 512, 0}, {64, 64, 2, 1024, 0}, {64, 64, 4, 1024, 0},
                              {64, 64, 6, 1024, 0}, {96, 64, 3, 1024, 0}, {96, 96, 3, 1024, 0}};
@@ -1661,8 +1663,6 @@ int cavity_autotune(cavity_t h, int32_t idx, const char* cache_path, cavity_tuni
       for (const Cand& c0 : (fp32 ? k32 : k64)) {
         for (int xcd = 0; xcd < 2; ++xcd) {
           const cav::SorConfig c{c0.tx, c0.ty, c0.s, c0.nt, xcd};
-          const int tiles = ((m.n + c.tx - 1) / c.tx) * ((m.n + c.ty - 1) / c.ty);
-          if (xcd && tiles % 8 != 0) continue;
           if (!cav::sor_config_supported(c, fp32)) continue;
           double us = 0;
           if ((rc = time_sweeps(h, m, c, fp32, launches + (launches & 1), &us)) != CAVITY_OK)

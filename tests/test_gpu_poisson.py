@@ -6,6 +6,7 @@ Every call goes through the C ABI (ctypes binding of libcavity.so).
   oracle's four-colour sweep applied k times (same ordering, same relaxation),
   to rounding.  Sizes are ragged against the tile size and span many tiles,
   so the halo logic of the temporally blocked kernel is exercised.
+* Every compiled FP64 tile configuration, the same way.
 * Converged solves: |psi_gpu - psi*| <= ||A^-1||_inf * ||r_gpu||_inf, where psi*
   is the oracle's exact discrete solution, ||A^-1||_inf is computed by the
   oracle (max of the solution for unit vorticity) and ||r_gpu|| is the final
@@ -33,9 +34,9 @@ def _inv_norm(n):
 
 
 # (n, sweeps): n <= 320 uses 32x32 tiles with 1 sweep per launch (pairs of 2),
-# larger n 64x64 tiles with 4 sweeps per launch (pairs of 8).
-@pytest.mark.parametrize("n,sweeps", [(5, 2), (33, 2), (64, 6), (97, 4), (330, 8), (400, 16),
-                                      (1024, 8)])
+# larger n 84x54 tiles with 5 sweeps per launch (pairs of 10).
+@pytest.mark.parametrize("n,sweeps", [(5, 2), (33, 2), (64, 6), (97, 4), (330, 10), (400, 20),
+                                      (1024, 10)])
 def test_fixed_sweeps_match_oracle_four_colour_sweeps(cav_mod, n, sweeps):
     print(f"[fixed sweeps] n={n} sweeps={sweeps}", flush=True)
     relax = 1.7
@@ -54,6 +55,38 @@ def test_fixed_sweeps_match_oracle_four_colour_sweeps(cav_mod, n, sweeps):
     assert np.max(np.abs(psi - ref)) <= 1e-13 * scale, np.max(np.abs(psi - ref)) / scale
     assert np.all(psi[0, :] == 0) and np.all(psi[-1, :] == 0)
     assert np.all(psi[:, 0] == 0) and np.all(psi[:, -1] == 0)
+
+
+# every compiled FP64 sweep configuration (tile x, tile y, sweeps per launch,
+# threads), in the XCD-banded tile order
+F64_CONFIGS = [(32, 32, 1, 256), (32, 32, 2, 256), (64, 32, 2, 512), (64, 64, 1, 1024),
+               (64, 64, 2, 1024), (64, 64, 3, 1024), (64, 64, 2, 512), (64, 64, 4, 512),
+               (64, 64, 4, 1024), (64, 64, 4, 768), (96, 64, 2, 1024), (96, 64, 3, 1024),
+               (92, 50, 4, 1024), (84, 54, 5, 1024)]
+
+
+@pytest.mark.parametrize("cfg", F64_CONFIGS)
+def test_every_fp64_tile_config_matches_oracle_sweeps(cav_mod, cfg):
+    """Two launch pairs, the second ending in a checking launch (wider halo):
+    ragged against every tile shape, with tile counts that are not multiples
+    of the eight XCDs."""
+    tx, ty, s, nt = cfg
+    n, relax = 777, 1.6
+    sweeps = 4 * s
+    print(f"[tile config] {cfg} n={n} sweeps={sweeps}", flush=True)
+    omega = inputs.random_field(n, seed=7)
+    c = cav_mod.Cavity(cav_mod.Params(n=n, re=1000.0, sor_omega=relax,
+                                      poisson_max_sweeps=sweeps))
+    c.set_tuning(tile_x=tx, tile_y=ty, sweeps_per_launch=s, threads=nt, xcd_bands=1,
+                 check_every=2 * s)
+    psi, info = c.poisson(0, omega, allow_noconv=True)
+    c.close()
+    assert info["sweeps"] == sweeps
+    ref = np.zeros((n, n))
+    for _ in range(sweeps):
+        ref = sor_four_colour_sweep(ref, omega, relax)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(psi - ref)) <= 1e-13 * scale, np.max(np.abs(psi - ref)) / scale
 
 
 def _converged_case(cav_mod, n, omega, precision, tol=1e-10):
