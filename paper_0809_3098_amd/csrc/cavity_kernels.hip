@@ -339,26 +339,33 @@ __device__ __forceinline__ void region_to_lds(const T* __restrict__ pin, int n, 
 #pragma unroll
   for (int q0 = 0; q0 < NL; q0 += CH) {
     T2 lv[CH];
-    bool st[CH];
+    bool st[CH], zy[CH];
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
       const int idx = tid + (q0 + j) * NT;
       lv[j].x = lv[j].y = T(0);
+      zy[j] = false;
       const int ly = idx / RXP;
       const int lx = 2 * (idx - ly * RXP);
       st[j] = q0 + j < NL && idx < NPAIR &&
               !(RING && lx >= G::H && lx < G::H + TX && ly >= G::H && ly < G::H + TY);
       if (st[j]) {
         const int gx = x0 + lx, gy = y0 + ly;
-        if ((unsigned)gy < (unsigned)n && gx >= 0) {
+        if ((unsigned)gy < (unsigned)n && (unsigned)gx < (unsigned)n) {
           const size_t g = (size_t)gy * pitch + gx;
           if (COHERENT) {
-            if (gx < n) lv[j].x = coh_load(pin + g);
+            lv[j].x = coh_load(pin + g);
             if (gx + 1 < n) lv[j].y = coh_load(pin + g + 1);
-          } else if (gx + 1 < n) {
+          } else {
+            // One 16-byte load per pair, even for the last pair of an odd
+            // grid: gx is even and the pitch even and above n - 1, so gx + 1
+            // is still inside the row; that node lies beyond the grid and is
+            // replaced by 0 when the pair is stored.  (A second, narrower
+            // load in another branch would write the same registers, and a
+            // select here would use the value: either makes the next load
+            // wait for this one.)
             lv[j] = *reinterpret_cast<const T2*>(pin + g);
-          } else if (gx < n) {
-            lv[j].x = pin[g];
+            zy[j] = gx + 1 >= n;
           }
         }
       }
@@ -370,7 +377,7 @@ __device__ __forceinline__ void region_to_lds(const T* __restrict__ pin, int n, 
         const int ly = idx / RXP;
         const int o = ((ly & 1) << 1) * G::PLANE + (ly >> 1) * G::RXH + (idx - ly * RXP);
         pl[o] = lv[j].x;
-        pl[o + G::PLANE] = lv[j].y;
+        pl[o + G::PLANE] = zy[j] ? T(0) : lv[j].y;
       }
     }
   }
@@ -385,24 +392,36 @@ __device__ __forceinline__ void rhs_to_regs(const T* __restrict__ F, int n, int 
                                             T (&fv)[4][SorGeom<T, TX, TY, S, NT, HX>::K]) {
   using G = SorGeom<T, TX, TY, S, NT, HX>;
   using T2 = typename Pair<T>::type;
+  // one pair load per lane and row, as for psi (gx + 1 stays inside the
+  // pitch); rhs_zero_beyond clears the node beyond an odd grid afterwards
+  const int gx = x0 + 2 * lane;
 #pragma unroll
   for (int cy = 0; cy < 2; ++cy) {
 #pragma unroll
     for (int r = 0; r < G::K; ++r) {
-      const int gx = x0 + 2 * lane, gy = y0 + 2 * (b0 + r) + cy;
+      const int gy = y0 + 2 * (b0 + r) + cy;
       T2 f;
       f.x = f.y = T(0);
-      if (lane < G::RXH && b0 + r < G::RYH && (unsigned)gy < (unsigned)n && gx >= 0) {
-        const size_t g = (size_t)gy * pitch + gx;
-        if (gx + 1 < n) {
-          f = *reinterpret_cast<const T2*>(F + g);
-        } else if (gx < n) {
-          f.x = F[g];
-        }
-      }
+      if (lane < G::RXH && b0 + r < G::RYH && (unsigned)gy < (unsigned)n &&
+          (unsigned)gx < (unsigned)n)
+        f = *reinterpret_cast<const T2*>(F + (size_t)gy * pitch + gx);
       fv[2 * cy][r] = f.x;
       fv[2 * cy + 1][r] = f.y;
     }
+  }
+}
+
+// The right-hand side of the node beyond an odd grid (x = n, in the pitch
+// padding) to 0.  Called once the following loads are issued too: using the
+// values earlier would make those loads wait.
+template <typename T, int TX, int TY, int S, int NT, int HX>
+__device__ __forceinline__ void rhs_zero_beyond(int n, int x0, int lane,
+                                                T (&fv)[4][SorGeom<T, TX, TY, S, NT, HX>::K]) {
+  if (x0 + 2 * lane + 1 < n) return;
+#pragma unroll
+  for (int cy = 0; cy < 2; ++cy) {
+#pragma unroll
+    for (int r = 0; r < SorGeom<T, TX, TY, S, NT, HX>::K; ++r) fv[2 * cy + 1][r] = T(0);
   }
 }
 
@@ -502,11 +521,14 @@ __device__ __forceinline__ void tile_residual(const T* pl,
 // One tile of S sweeps, shared by the per-launch kernel and the persistent
 // batched kernel.  sp is the block's LDS.  With CHECK the block-wide maxima
 // of |g - psi| and |psi| over the tile are returned in thread 0's rmax / pmax.
+// run = false (block-uniform) ends the tile once its loads are done, before
+// any sweep or store, and returns false: a caller whose go-ahead is itself a
+// memory read passes it here so that its latency overlaps the region loads.
 template <typename T, int TX, int TY, int S, int NT, int HX, bool COH = false>
-__device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restrict__ pout,
+__device__ __forceinline__ bool sor_tile(const T* __restrict__ pin, T* __restrict__ pout,
                                          const T* __restrict__ F, int n, int pitch, int tile,
                                          int tiles_x, T w, T* sp, bool CHECK, double& rmax_out,
-                                         double& pmax_out) {
+                                         double& pmax_out, bool run = true) {
   using G = SorGeom<T, TX, TY, S, NT, HX>;
   constexpr int K = G::K;
   T* const pl = sp + G::BASE;  // first parity plane
@@ -522,9 +544,13 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
   const int b0 = wave * K;         // first owned row of every plane
   T fv[4][K];
   T pv[4][K];
-  region_to_lds<T, TX, TY, S, NT, HX, false, 0, COH>(pin, n, pitch, x0, y0, pl, tid);
+  // F first: its loads are in flight while those of psi are issued, and the
+  // wait for psi before its LDS stores covers both
   rhs_to_regs<T, TX, TY, S, NT, HX>(F, n, pitch, x0, y0, lane, b0, fv);
+  region_to_lds<T, TX, TY, S, NT, HX, false, 0, COH>(pin, n, pitch, x0, y0, pl, tid);
+  rhs_zero_beyond<T, TX, TY, S, NT, HX>(n, x0, lane, fv);
   __syncthreads();
+  if (!run) return false;
   lds_to_regs<T, TX, TY, S, NT, HX, false>(pl, lane, b0, pv);
   const int lxd0 = 1 - x0, lxd1 = n - 2 - x0;  // domain interior in local coordinates
   const int lyd0 = 1 - y0, lyd1 = n - 2 - y0;
@@ -535,6 +561,7 @@ __device__ __forceinline__ void sor_tile(const T* __restrict__ pin, T* __restric
     tile_residual<T, TX, TY, S, NT, HX>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, rmax, pmax);
   rmax_out = rmax;
   pmax_out = pmax;
+  return true;
 }
 
 template <typename T, int TX, int TY, int S, int NT, bool CHECK>
@@ -545,8 +572,13 @@ __global__ __launch_bounds__(NT) void k_sor(const T* __restrict__ pin, T* __rest
   constexpr int HX = CHECK ? 2 : 0;
   using G = SorGeom<T, TX, TY, S, NT, HX>;
   __shared__ T sp[G::SLOTS];
-  if (ctl->state != SOLVE_RUN) return;
-  const T w = (T)(relax_arg > 0.0 ? relax_arg : ctl->relax);
+  // A launch enqueued after its solve stopped returns without a sweep or a
+  // store.  The state is read first but tested only after the region loads
+  // (inside sor_tile), so its latency overlaps theirs: vector loads, which
+  // complete in order with the region's, where a scalar load would be waited
+  // for together with the kernel arguments before the first region load.
+  const bool run = coh_load(&ctl->state) == SOLVE_RUN;
+  const T w = (T)(relax_arg > 0.0 ? relax_arg : coh_load(&ctl->relax));
   // XCD bands: blocks are dealt to the eight XCDs in turn (block b to XCD
   // b mod 8), so XCD x gets a contiguous band of tiles, nb / 8 of them plus
   // one for the first nb mod 8 XCDs; neighbouring tiles then share an L2.
@@ -557,8 +589,9 @@ __global__ __launch_bounds__(NT) void k_sor(const T* __restrict__ pin, T* __rest
     tile = x * q + min(x, r) + (blockIdx.x >> 3);
   }
   double rmax = 0.0, pmax = 0.0;
-  sor_tile<T, TX, TY, S, NT, HX>(pin, pout, F, n, pitch, tile, tiles_x, w, sp, CHECK, rmax,
-                                 pmax);
+  if (!sor_tile<T, TX, TY, S, NT, HX>(pin, pout, F, n, pitch, tile, tiles_x, w, sp, CHECK, rmax,
+                                      pmax, run))
+    return;
   // A checking launch only leaves its per-block maxima; k_decide, the next
   // launch on the stream, reduces them.  The kernel boundary orders the
   // stores, so no block pays for a device-wide release fence.
@@ -946,6 +979,7 @@ __global__ __launch_bounds__(NT) void k_sor_resident(double* __restrict__ bufa,
   double w = ctl->relax;
   region_to_lds<double, TX, TY, S, NT, 0, false>(bufa, n, pitch, x0, y0, pl, tid);
   rhs_to_regs<double, TX, TY, S, NT, 0>(F, n, pitch, x0, y0, lane, b0, fv);
+  rhs_zero_beyond<double, TX, TY, S, NT, 0>(n, x0, lane, fv);
   __syncthreads();
   lds_to_regs<double, TX, TY, S, NT, 0, false>(pl, lane, b0, pv);
   int r = 0;
@@ -1498,6 +1532,9 @@ inline dim3 grid2d(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); 
 template <typename T, int TX, int TY, int S, int NT>
 hipError_t sor_launch(const T* pin, T* pout, const T* F, int n, int pitch, PoissonCtl* ctl,
                       double* part, int check, int xcd_bands, double relax, hipStream_t st) {
+  // the tile loads read node pairs (x even, x + 1): the pitch must be even
+  // and hold x = n for odd n
+  if ((pitch & 1) || pitch < n + (n & 1)) return hipErrorInvalidValue;
   const int tx = (n + TX - 1) / TX, ty = (n + TY - 1) / TY;
   const dim3 grid(tx * ty);
   if (check) {

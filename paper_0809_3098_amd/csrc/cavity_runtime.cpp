@@ -167,6 +167,8 @@ namespace {
     }                                                                            \
   } while (0)
 
+// Row pitch of every field, in nodes: a multiple of 32, so even and, for odd
+// n, at least n + 1 (the sweep kernels load node pairs x, x + 1 with x even).
 int pitch_of(int n) { return (n + 31) / 32 * 32; }
 
 // Residual-check spacing (FP64) and inner sweeps per refinement round
