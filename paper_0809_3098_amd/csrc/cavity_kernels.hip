@@ -181,6 +181,30 @@ template <> struct Pair<float> { using type = float2; };
 
 // One colour pass C (parity class (C & 1, C >> 1)) of pass number k over the
 // nodes this thread owns.  sp points at the first plane.
+//
+// Thread (wave q, lane l) owns the nodes x = 2l, 2l + 1 and y = 2b, 2b + 1 for
+// the K plane rows b = b0 ... b0 + K - 1 of its strip: a 2 x 2K block holding
+// all four colours, kept in pv.  The owner is the only thread that updates a
+// node, so pv is always current, and a node's eight neighbours are
+//   * E / W: the other-x-parity node of the same row, in pv, and the same
+//     colour in the adjacent lane (DPP wavefront shift);
+//   * N / S: the other-y-parity nodes of rows b and b -/+ 1, in pv except the
+//     row beyond the strip's end;
+//   * diagonals: as N / S in the fourth colour, with the lane shift.
+// Only that row beyond the strip (below its first row for cy = 0, above its
+// last for cy = 1) crosses to another wavefront: it is read from LDS, where
+// its owner publishes it.  After updating colour C a strip therefore
+// publishes one row: its first for cy = 0 (read by the strip below in the
+// cy = 1 passes), its last for cy = 1 (read by the strip above in the next
+// sweep's cy = 0 passes).  Passes 0 and 1 read only what passes 2 and 3 of
+// the previous sweep published, passes 2 and 3 only what passes 0 and 1
+// published, so a barrier after passes 1 and 3 orders every exchange and
+// also keeps each published row from being overwritten while still read.
+//
+// Lanes outside the pass relax with 0 (they keep their value) so the pass
+// has no divergent branch; rows outside it are skipped (wave-uniform).  Only
+// the edge nodes of the region lack a neighbour (cx = 0: lane 0; cx = 1: the
+// last column; the first and last plane rows), and no pass updates them.
 template <typename T, int TX, int TY, int S, int NT, int HX, int C>
 __device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
                                             const T (&fv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
@@ -189,69 +213,66 @@ __device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][SorGeom<T, TX, TY,
   using G = SorGeom<T, TX, TY, S, NT, HX>;
   constexpr int K = G::K;
   constexpr int cx = C & 1, cy = C >> 1;
+  constexpr int EW = cy * 2 + (1 - cx), NS = (1 - cy) * 2 + cx, DG = (1 - cy) * 2 + (1 - cx);
   const int lxlo = max(k, lxd0), lxhi = min(G::RX - 1 - k, lxd1);
   const int lylo = max(k, lyd0), lyhi = min(G::RY - 1 - k, lyd1);
   const int a0 = (lxlo - cx + 1) >> 1, a1 = (lxhi - cx) >> 1;
   // the strip's rows inside the pass (wave-uniform)
   const int r_lo = max((lylo - cy + 1) >> 1, b0) - b0;
   const int r_hi = min((lyhi - cy) >> 1, b0 + K - 1) - b0;
-  T* own = sp + C * G::PLANE;
-  const T* ew = sp + (cy * 2 + (1 - cx)) * G::PLANE;
-  const T* ns = sp + ((1 - cy) * 2 + cx) * G::PLANE;
-  const T* dg = sp + ((1 - cy) * 2 + (1 - cx)) * G::PLANE;
-  // Lane l holds column l of every plane.  A node of x parity cx = 0 (at
-  // 2l) has its east neighbours in column l of the odd-x planes and its west
-  // ones in column l - 1, the left lane's; for cx = 1 (at 2l + 1) the west
-  // ones are in column l and the east ones in the right lane's column l + 1.
-  // Only region-edge nodes lack that lane (cx = 0: lane 0, x = 0; cx = 1: the
-  // last column, x = RX - 1), and no pass updates them, so every neighbour is
-  // one LDS read of the lane's own column plus one DPP shift.
   const int ic = min(lane, G::RXH - 1);
   constexpr int kOther = cx == 0 ? kDppShr1 : kDppShl1;
-  // Lanes outside the pass relax with 0: they keep their value (held in pv,
-  // equal to the plane's) and store it back, so the pass has no divergent
-  // branch; lanes beyond a plane row store to the sink.
   const T wl = (lane >= a0 && lane <= a1) ? w : T(0);
-  const int wr = lane < G::RXH ? b0 * G::RXH + lane : G::SINK - G::BASE - C * G::PLANE + lane;
-  const int wstep = lane < G::RXH ? G::RXH : 0;
   const T c4 = T(0.2), cd = T(0.05);
   if (r_lo <= r_hi) {
-    // The south row of the strip's first row; every later row takes the
-    // north values of the row below it.  Rows outside the pass are read too
-    // (the padding keeps them inside LDS), so the chain has no selects.
-    const int rs0 = (b0 + cy - 1) * G::RXH + ic;
-    T sS = ns[rs0];
-    T dS = dg[rs0];
+    // S-side values of the first row and the N-side values beyond the last:
+    // the row outside the strip comes from LDS (the padding rows keep it
+    // inside LDS; its values are only used for rows inside the pass)
+    T sS, dS, bN = T(0), bdN = T(0);
+    if (cy == 0) {
+      sS = sp[NS * G::PLANE + (b0 - 1) * G::RXH + ic];
+      dS = sp[DG * G::PLANE + (b0 - 1) * G::RXH + ic];
+    } else {
+      sS = pv[NS][0];
+      dS = pv[DG][0];
+      bN = sp[NS * G::PLANE + (b0 + K) * G::RXH + ic];
+      bdN = sp[DG * G::PLANE + (b0 + K) * G::RXH + ic];
+    }
     T dSo = lane_shift<kOther>(dS);
 #pragma unroll
     for (int r = 0; r < K; ++r) {
-      const int b = b0 + r;
-      const int rn = (b + cy) * G::RXH + ic;
-      const T sN = ns[rn];
-      const T dN = dg[rn];
+      const T sN = cy == 0 ? pv[NS][r] : (r + 1 < K ? pv[NS][r + 1] : bN);
+      const T dN = cy == 0 ? pv[DG][r] : (r + 1 < K ? pv[DG][r + 1] : bdN);
       const T dNo = lane_shift<kOther>(dN);
       if (r >= r_lo && r <= r_hi) {  // wave-uniform
-        const T e = ew[b * G::RXH + ic];
+        const T e = pv[EW][r];
         const T eo = lane_shift<kOther>(e);
         const T s4 = (e + eo) + (sN + sS);
         const T sd = (dN + dNo) + (dS + dSo);
         const T p = pv[C][r];
         const T g = fma_t(c4, s4, fma_t(cd, sd, fv[C][r]));
-        const T np = fma_t(wl, g - p, p);
-        pv[C][r] = np;
-        own[wr + r * wstep] = np;
+        pv[C][r] = fma_t(wl, g - p, p);
       }
       sS = sN;
       dS = dN;
       dSo = dNo;
     }
+    // publish the strip's boundary row of colour C (lanes beyond a plane row
+    // store to the sink)
+    constexpr int rp = cy == 0 ? 0 : K - 1;
+    if (b0 + rp < G::RYH) {
+      const int o = lane < G::RXH ? C * G::PLANE + (b0 + rp) * G::RXH + lane
+                                  : G::SINK - G::BASE + lane;
+      sp[o] = pv[C][rp];
+    }
   }
-  __syncthreads();
+  if (C == 1 || C == 3) __syncthreads();
 }
 
 // Residual of colour C over the tile's own interior nodes after the sweeps:
 // max |g - psi| and max |psi| accumulated into rmax / pmax.  Same neighbour
-// reads and the same arithmetic as the update, no stores.
+// values and the same arithmetic as the update, no stores; called after the
+// sweeps' final barrier, when every published boundary row is current.
 template <typename T, int TX, int TY, int S, int NT, int HX, int C>
 __device__ __forceinline__ void residual_pass(const T* pl,
                                               const T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
@@ -261,32 +282,35 @@ __device__ __forceinline__ void residual_pass(const T* pl,
   using G = SorGeom<T, TX, TY, S, NT, HX>;
   constexpr int K = G::K;
   constexpr int cx = C & 1, cy = C >> 1;
+  constexpr int EW = cy * 2 + (1 - cx), NS = (1 - cy) * 2 + cx, DG = (1 - cy) * 2 + (1 - cx);
   const int lxlo = max(G::H, lxd0), lxhi = min(G::H + TX - 1, lxd1);
   const int lylo = max(G::H, lyd0), lyhi = min(G::H + TY - 1, lyd1);
   const int a0 = (lxlo - cx + 1) >> 1, a1 = (lxhi - cx) >> 1;
   const int r_lo = max((lylo - cy + 1) >> 1, b0) - b0;
   const int r_hi = min((lyhi - cy) >> 1, b0 + K - 1) - b0;
   if (r_lo > r_hi) return;
-  const T* ew = pl + (cy * 2 + (1 - cx)) * G::PLANE;
-  const T* ns = pl + ((1 - cy) * 2 + cx) * G::PLANE;
-  const T* dg = pl + ((1 - cy) * 2 + (1 - cx)) * G::PLANE;
   const int ic = min(lane, G::RXH - 1);
   constexpr int kOther = cx == 0 ? kDppShr1 : kDppShl1;
   const bool lane_in = lane >= a0 && lane <= a1;
   const T c4 = T(0.2), cd = T(0.05);
-  const int rs0 = (b0 + cy - 1) * G::RXH + ic;
-  T sS = ns[rs0];
-  T dS = dg[rs0];
+  T sS, dS, bN = T(0), bdN = T(0);
+  if (cy == 0) {
+    sS = pl[NS * G::PLANE + (b0 - 1) * G::RXH + ic];
+    dS = pl[DG * G::PLANE + (b0 - 1) * G::RXH + ic];
+  } else {
+    sS = pv[NS][0];
+    dS = pv[DG][0];
+    bN = pl[NS * G::PLANE + (b0 + K) * G::RXH + ic];
+    bdN = pl[DG * G::PLANE + (b0 + K) * G::RXH + ic];
+  }
   T dSo = lane_shift<kOther>(dS);
 #pragma unroll
   for (int r = 0; r < K; ++r) {
-    const int b = b0 + r;
-    const int rn = (b + cy) * G::RXH + ic;
-    const T sN = ns[rn];
-    const T dN = dg[rn];
+    const T sN = cy == 0 ? pv[NS][r] : (r + 1 < K ? pv[NS][r + 1] : bN);
+    const T dN = cy == 0 ? pv[DG][r] : (r + 1 < K ? pv[DG][r + 1] : bdN);
     const T dNo = lane_shift<kOther>(dN);
     if (r >= r_lo && r <= r_hi) {  // wave-uniform
-      const T e = ew[b * G::RXH + ic];
+      const T e = pv[EW][r];
       const T eo = lane_shift<kOther>(e);
       const T s4 = (e + eo) + (sN + sS);
       const T sd = (dN + dNo) + (dS + dSo);
