@@ -227,23 +227,27 @@ int derive(const cavity_params& p, Member& m) {
   // A stalled over-relaxation sits at its rounding floor; allow several
   // residual halvings' worth of sweeps (about 0.11 (n-1) each) before polishing.
   m.stall_window = std::max<long long>(64, 2LL * p.n);
-  // tiles: small grids favour more, smaller blocks.  A launch of 1024
-  // threads costs about a fixed part (start, region load, store) plus, per
-  // sweep, the plane rows each wavefront walks; a region row is at most 128
-  // nodes (64 per parity plane, one per lane).  Measured on MI355X: at
-  // 1024^2, 84 x 54 tiles with 5 sweeps per launch (FP64; 247 tiles, one per
-  // CU, three plane rows per wavefront, full 64-lane rows) take 3.5 us per
-  // sweep against 3.9 for 64 x 64 with 4; FP32 keeps 64 x 64 with 6.  At
-  // 4096^2, 96 x 64 tiles with 3 sweeps.  XCD-banded tile order throughout.
+  // tiles: small grids favour more, smaller blocks.  A launch costs about a
+  // fixed part (start, region load, store) plus, per sweep, the plane rows
+  // each wavefront walks; a region row is at most 128 nodes (64 per parity
+  // plane, one per lane).  Measured on MI355X: at 1024^2, 84 x 54 tiles with
+  // 5 sweeps per launch and 1024 threads (FP64; 247 tiles, one per CU, three
+  // plane rows per wavefront, full 64-lane rows), XCD-banded: 2.9 us per
+  // sweep against 3.1 for 64 x 64 with 4.  At 4096^2, 64 x 64 tiles with 4
+  // sweeps and 512 threads (FP64, two blocks per CU overlap each other's
+  // loads: 37.6 us per sweep against 47.7 for 96 x 64 with 3 and 1024
+  // threads).  FP32 (no checking launches, so no wider halo): 88 x 56 tiles
+  // with 5 sweeps at both sizes (2.38 / 20.0 us against 2.42 / 21.1 for the
+  // next best).
   if (p.n <= 320) {
     m.cfg64 = {32, 32, 1, 256, 0};
     m.cfg32 = {32, 32, 1, 256, 0};
   } else if (p.n <= 2048) {
     m.cfg64 = {84, 54, 5, 1024, 1};
-    m.cfg32 = {64, 64, 6, 1024, 1};
+    m.cfg32 = {88, 56, 5, 1024, 1};
   } else {
-    m.cfg64 = {96, 64, 3, 1024, 1};
-    m.cfg32 = {96, 64, 3, 1024, 1};
+    m.cfg64 = {64, 64, 4, 512, 0};
+    m.cfg32 = {88, 56, 5, 1024, 1};
   }
   // Residual checks every n/16 sweeps (4 to 64): a solve needs O(n) sweeps,
   // so the overshoot past convergence stays a fixed small fraction while the
@@ -373,7 +377,12 @@ void carve(Member& m, char*& cur) {
 }
 
 // Multigrid smoothing kernels: four-colour sweeps, 2 per launch.
+// Smoother launches of the V-cycles (two sweeps each).  Above 2048 nodes a
+// side, 512-thread blocks: two share a CU, so one block's loads and stores
+// overlap the other's sweeps (measured at 4096^2: 43.8 against 67.4 us per
+// FP64 sweep with 1024 threads).
 cav::SorConfig mg_cfg(int n) {
+  if (n > 2048) return cav::SorConfig{64, 64, 2, 512, 0};
   return n > 320 ? cav::SorConfig{64, 64, 2, 1024, 0} : cav::SorConfig{32, 32, 2, 256, 0};
 }
 constexpr int kMgNu = 2;   // pre- and post-smoothing sweeps (one launch each)
@@ -1652,7 +1661,8 @@ int cavity_autotune(cavity_t h, int32_t idx, const char* cache_path, cavity_tuni
                              {84, 54, 5, 1024, 0}};
   static const std::vector<Cand> k32 = {{32, 32, 1, 256, 0}, {32, 32, 2, 256, 0}, {64, 32, 2, 512, 0},
                              {64, 64, 2, 512, 0}, {64, 64, 2, 1024, 0}, {64, 64, 4, 1024, 0},
-                             {64, 64, 6, 1024, 0}, {96, 64, 3, 1024, 0}, {96, 96, 3, 1024, 0}};
+                             {64, 64, 6, 1024, 0}, {96, 64, 3, 1024, 0}, {96, 96, 3, 1024, 0},
+                             {88, 56, 5, 1024, 0}, {64, 64, 4, 512, 0},  {64, 64, 6, 512, 0}};
   if (idx >= 0) {
     Member& m = h->m[idx];
     // 1. tile shape, sweeps per launch and tile order, by sweep time

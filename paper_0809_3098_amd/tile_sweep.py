@@ -17,7 +17,7 @@ F64 = [(32, 32, 1, 256), (32, 32, 2, 256), (64, 32, 2, 512), (64, 64, 1, 1024),
        (92, 50, 4, 1024), (84, 54, 5, 1024)]
 F32 = [(32, 32, 1, 256), (32, 32, 2, 256), (64, 32, 2, 512), (64, 64, 2, 512),
        (64, 64, 2, 1024), (64, 64, 4, 1024), (64, 64, 6, 1024), (96, 64, 3, 1024),
-       (96, 96, 3, 1024)]
+       (96, 96, 3, 1024), (88, 56, 5, 1024), (64, 64, 4, 512), (64, 64, 6, 512)]
 
 
 def main(sizes):

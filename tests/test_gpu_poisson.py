@@ -6,7 +6,8 @@ Every call goes through the C ABI (ctypes binding of libcavity.so).
   oracle's four-colour sweep applied k times (same ordering, same relaxation),
   to rounding.  Sizes are ragged against the tile size and span many tiles,
   so the halo logic of the temporally blocked kernel is exercised.
-* Every compiled FP64 tile configuration, the same way.
+* Every compiled FP64 tile configuration, the same way; every FP32 one
+  through a converged mixed-precision solve.
 * Converged solves: |psi_gpu - psi*| <= ||A^-1||_inf * ||r_gpu||_inf, where psi*
   is the oracle's exact discrete solution, ||A^-1||_inf is computed by the
   oracle (max of the solution for unit vorticity) and ||r_gpu|| is the final
@@ -87,6 +88,32 @@ def test_every_fp64_tile_config_matches_oracle_sweeps(cav_mod, cfg):
         ref = sor_four_colour_sweep(ref, omega, relax)
     scale = np.max(np.abs(ref))
     assert np.max(np.abs(psi - ref)) <= 1e-13 * scale, np.max(np.abs(psi - ref)) / scale
+
+
+F32_CONFIGS = [(32, 32, 1, 256), (32, 32, 2, 256), (64, 32, 2, 512), (64, 64, 2, 512),
+               (64, 64, 2, 1024), (64, 64, 4, 1024), (64, 64, 6, 1024), (96, 64, 3, 1024),
+               (96, 96, 3, 1024), (88, 56, 5, 1024), (64, 64, 4, 512), (64, 64, 6, 512)]
+
+
+@pytest.mark.parametrize("cfg", F32_CONFIGS)
+def test_every_fp32_tile_config_converges_to_oracle(cav_mod, cfg):
+    """Mixed precision: the FP32 correction sweeps of each configuration
+    drive the FP64-refined solve to the tolerance, and the result meets the
+    error bound against the oracle's exact solution."""
+    tx, ty, s, nt = cfg
+    n = 777
+    print(f"[fp32 tile config] {cfg} n={n}", flush=True)
+    omega = inputs.random_field(n, seed=9, scale=0.02)
+    c = cav_mod.Cavity(cav_mod.Params(n=n, re=1000.0, poisson_tol=1e-10, precision=1))
+    c.set_tuning(tile_x32=tx, tile_y32=ty, sweeps_per_launch32=s, threads32=nt, xcd_bands=1)
+    psi, info = c.poisson(0, omega)
+    c.close()
+    ref = poisson_solve(omega)
+    err = np.max(np.abs(psi - ref))
+    bound = 1.02 * _inv_norm(n) * info["resid_inf"] + 1e-14 * np.max(np.abs(ref))
+    assert info["status"] == 0
+    assert info["resid_inf"] <= 1e-10 or info["floor_limited"] == 1
+    assert err <= bound, (err, bound, info)
 
 
 def _converged_case(cav_mod, n, omega, precision, tol=1e-10):
