@@ -120,10 +120,19 @@ struct Member {
   double t = 0;
   long long sweeps_total = 0, sweeps_step = 0;
   double est_sweeps = 0;  // running estimate of sweeps per solve
+  // sweeps of the last solve of each stage of a step (index 1..5): a stage's
+  // count repeats from step to step far better than consecutive stages'
+  double est_stage[6] = {0, 0, 0, 0, 0, 0};
   int floor_step = 0;
   int status_step = CAVITY_OK;
   double last_resid = 0;
 };
+
+// Forget the sweep estimates (a new schedule or relaxation changes them).
+void reset_estimates(Member& m) {
+  m.est_sweeps = 0;
+  for (double& e : m.est_stage) e = 0;
+}
 
 }  // namespace
 
@@ -583,7 +592,10 @@ int enqueue_resident(cavity_s* h, Member& m, const cav::SorConfig& c) {
 
 // state_solve: the solve produces the state's psi (refresh its FP32 shadow);
 // false for solves into scratch buffers.
-int solve_members(cavity_s* h, const std::vector<int>& idx, bool state_solve = true) {
+// stage: the SSPRK stage (1..5) the solves belong to, 0 for any other solve;
+// it selects the sweep estimate that sizes the first chunk of launches.
+int solve_members(cavity_s* h, const std::vector<int>& idx, bool state_solve = true,
+                  int stage = 0) {
   int rc;
   std::vector<int> active, resident;
   for (int k : idx) {
@@ -604,11 +616,18 @@ int solve_members(cavity_s* h, const std::vector<int>& idx, bool state_solve = t
     for (int k : active) {
       Member& m = h->m[k];
       const long long per_unit = unit_sweeps(m);
+      // Launches enqueued past the device's decision still cost a few us
+      // each, a chunk that falls short one more host round trip: the first
+      // chunk covers the estimate with a small margin, later ones add a few
+      // per cent of it (a quarter of what is enqueued when nothing is known).
+      const double est = stage > 0 && m.est_stage[stage] > 0 ? m.est_stage[stage] : m.est_sweeps;
       long long units;
-      if (first && m.est_sweeps > 0)
-        units = (long long)std::ceil(1.05 * m.est_sweeps / per_unit);
+      if (first && est > 0)
+        units = (long long)std::ceil(1.02 * est / per_unit);
       else if (first)
         units = std::max<long long>(4, (long long)(0.5 * (m.n - 1) / per_unit));
+      else if (est > 0)
+        units = std::max<long long>(1, (long long)std::ceil(0.05 * est / per_unit));
       else
         units = std::max<long long>(2, enqueued[k] / 4);
       units = std::max<long long>(1, std::min<long long>(units, m.max_sweeps / per_unit + 1));
@@ -653,8 +672,10 @@ int solve_members(cavity_s* h, const std::vector<int>& idx, bool state_solve = t
     m.sweeps_step += c.sweeps;
     m.sweeps_total += c.sweeps;
     m.last_resid = c.last * (10.0 / 3.0) / (m.h * m.h);
-    if (c.sweeps > 0)
+    if (c.sweeps > 0) {
       m.est_sweeps = m.est_sweeps > 0 ? 0.5 * (m.est_sweeps + c.sweeps) : (double)c.sweeps;
+      if (stage > 0) m.est_stage[stage] = (double)c.sweeps;
+    }
     if (c.state == cav::SOLVE_FLOOR) m.floor_step = 1;
     if (c.state == cav::SOLVE_NONFINITE) {
       h->poisoned = true;
@@ -971,7 +992,7 @@ int step_all(cavity_s* h, bool want_diag) {
       if ((rc = enqueue_stage(h, stage)) != CAVITY_OK) return rc;
       for (int k : fixed)
         if ((rc = enqueue_fixed(h, h->m[k])) != CAVITY_OK) return rc;
-      rc = solved.empty() ? CAVITY_OK : solve_members(h, solved);
+      rc = solved.empty() ? CAVITY_OK : solve_members(h, solved, true, stage);
       if (rc == CAVITY_ENONFINITE || rc == CAVITY_EHIP) return rc;
       if (rc != CAVITY_OK) worst = rc;
       if ((rc = enqueue_thom(h, stage)) != CAVITY_OK) return rc;
@@ -1631,7 +1652,7 @@ int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t) {
   m.cfg32 = c32;
   m.relax = t->sor_omega;
   set_schedule(m, t->check_every, t->inner_sweeps);
-  m.est_sweeps = 0;
+  reset_estimates(m);
   destroy_graphs(h);  // captured launches carry the old configuration and relaxation
   return CAVITY_OK;
 }
@@ -1718,7 +1739,7 @@ int cavity_autotune(cavity_t h, int32_t idx, const char* cache_path, cavity_tuni
       }
     }
     set_schedule(m, best_ce, best_in);
-    m.est_sweeps = 0;
+    reset_estimates(m);
     destroy_graphs(h);
     if ((rc = cavity_get_tuning(h, idx, &t)) != CAVITY_OK) return rc;
   } else {
