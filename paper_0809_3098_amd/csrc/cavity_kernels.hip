@@ -4,8 +4,10 @@
 // are pitched row-major [j][i] (x fastest); walls at i, j in {0, n-1}; the
 // lid is row n-1.  h = 1/(n-1) on the unit square.
 //
-// Stencil work here is bandwidth- or LDS-bound, not a dense contraction, so
-// no matrix cores are used.  Wavefronts are 64 lanes; blocks are 256 threads.
+// Stencil work here is bound by memory bandwidth, by on-chip data movement
+// or by synchronisation, never a dense contraction, so no matrix cores are
+// used.  Wavefronts are 64 lanes; the elementwise kernels use 256-thread
+// blocks, the sweep kernels 256 to 1024 threads (one tile per block).
 
 #include <float.h>
 #include <math.h>
