@@ -306,7 +306,15 @@ def main():
             cells = sum(m * m for _, m in b["members"])
             cb = Cavity([Params(n=m, re=r, poisson_tol=b["tol"], precision=prec_b)
                          for r, m in b["members"]], device="cuda:0", stream=stream)
+            default_exec = cb.exec_mode()
+            cb.set_exec(EXEC["graph"])
             el, _ = _timed_steps(torch, cb, args.extra_steps, 1)
+            cb.close()
+            # the same batch in stream execution: one stream per cavity
+            cb = Cavity([Params(n=m, re=r, poisson_tol=b["tol"], precision=prec_b)
+                         for r, m in b["members"]], device="cuda:0", stream=stream)
+            cb.set_exec(EXEC["stream"])
+            el_st, _ = _timed_steps(torch, cb, args.extra_steps, 1)
             cb.close()
             seq = 0.0
             for r, m in b["members"]:
@@ -318,8 +326,11 @@ def main():
             extras[f"{wname}_{label}"] = {
                 "cells": cells,
                 "batched_graph_mcell_steps_s": round(cells * args.extra_steps / el / 1e6, 4),
+                "batched_streams_mcell_steps_s": round(cells * args.extra_steps / el_st / 1e6, 4),
                 "sequential_stream_mcell_steps_s": round(cells * args.extra_steps / seq / 1e6, 4),
-                "speedup": round(seq / el, 3), "steps": args.extra_steps}
+                "speedup": round(seq / el, 3), "speedup_streams": round(seq / el_st, 3),
+                "default_exec": {v: k for k, v in EXEC.items()}[default_exec],
+                "steps": args.extra_steps}
 
     cpu = None if args.no_cpu else _cpu_baseline(n, wl["re"], args.cpu_steps)
     line = {

@@ -272,7 +272,13 @@ int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t);
  * How cavity_step runs the Poisson solves.
  *   CAVITY_EXEC_STREAM      one launch per S sweeps, every cavity on its own;
  *                           the host reads each solve's decision once per chunk
- *                           of enqueued launches (default for one cavity).
+ *                           of enqueued launches (default for one cavity, and
+ *                           for several when one has n > 512).
+ *                           With several cavities each runs on a stream of its
+ *                           own (created by the handle, default priority),
+ *                           forked from the handle's stream at the start of a
+ *                           step and joined back at its end, so that small
+ *                           cavities use the CUs a large one leaves idle.
  *   CAVITY_EXEC_PERSISTENT  one persistent launch per stage solves every cavity
  *                           of the handle (tile list over all cavities, grid
  *                           barriers between sweep rounds, per-cavity stopping
@@ -290,7 +296,9 @@ int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t);
  *                           STREAM.
  *   CAVITY_EXEC_GRAPH       as PERSISTENT, with the whole step (five stages)
  *                           captured once per buffer parity in a hipGraph and
- *                           replayed (default for count > 1).  When every
+ *                           replayed (default for count > 1 when every cavity
+ *                           has n <= 512: cavities too small to fill the GPU
+ *                           alone are fused into one launch).  When every
  *                           cavity is in the coupled mode (fixed_sweeps > 0)
  *                           the graph holds the per-launch sweeps instead.
  * Both persistent modes need one precision for all cavities and the SOR

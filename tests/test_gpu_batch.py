@@ -67,7 +67,9 @@ def test_reynolds_sweep_six_cavities_graph(cm):
     steps = 3
     print("[re sweep] six cavities", flush=True)
     c = cm.Cavity([cm.Params(n=n, re=re) for re, n in members])
-    assert c.exec_mode() == cm.CAVITY_EXEC_GRAPH
+    # cavities this large default to a stream each; the graph is still there
+    assert c.exec_mode() == cm.CAVITY_EXEC_STREAM
+    c.set_exec(cm.CAVITY_EXEC_GRAPH)
     stats = c.step(steps)
     fields = [c.fields(k) for k in range(len(members))]
     c.close()

@@ -130,6 +130,42 @@ def test_batch_streams_equal_sequential(cm):
         assert stats[k]["sweeps_last_step"] == st["sweeps_last_step"]
 
 
+def test_streams_per_cavity_every_kind_bitwise(cm):
+    """Stream execution of several cavities runs each on its own stream: FP64
+    SOR, mixed precision, multigrid and the coupled mode side by side give
+    bitwise the results of one handle each, step by step."""
+    kinds = [dict(n=200, re=3000.0), dict(n=257, re=5000.0, precision=cm.CAVITY_MIXED),
+             dict(n=130, re=2000.0), dict(n=97, re=1000.0, fixed_sweeps=6, sor_omega=0.7)]
+    steps = 3
+    print(f"[streams per cavity] {kinds}", flush=True)
+
+    def make(ps):
+        c = cm.Cavity([cm.Params(**p) for p in ps])
+        c.set_exec(cm.CAVITY_EXEC_STREAM)
+        for k, p in enumerate(ps):
+            if p["n"] == 130:
+                c.set_tuning(k, solver=cm.CAVITY_SOLVER_MG)
+        return c
+
+    c = make(kinds)
+    solo = []
+    for p in kinds:
+        s = make([p])
+        solo.append(s)
+    for step in range(steps):
+        stats = c.step(1)
+        for k, s in enumerate(solo):
+            st = s.step(1)[0]
+            pg, wg = c.fields(k)[:2]
+            ps_, ws = s.fields()[:2]
+            assert np.array_equal(pg, ps_) and np.array_equal(wg, ws), (step, k)
+            assert stats[k]["sweeps_last_step"] == st["sweeps_last_step"], (step, k)
+            assert stats[k]["ke"] == st["ke"], (step, k)
+    c.close()
+    for s in solo:
+        s.close()
+
+
 def test_noise_start_matches_oracle(cm):
     n, re, steps = 65, 3.0e4, 10
     print(f"[noise start] n={n}", flush=True)
