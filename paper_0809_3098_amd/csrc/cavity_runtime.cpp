@@ -1030,13 +1030,25 @@ struct Fan {
 
 int fan_out(cavity_s* h, Fan& f) {
   if (h->mst.empty()) {
-    h->mst.assign(h->count, nullptr);
-    h->mev.assign(h->count, nullptr);
-    for (int k = 0; k < h->count; ++k) {
-      HIP_TRY(h, hipStreamCreateWithFlags(&h->mst[k], hipStreamNonBlocking));
-      HIP_TRY(h, hipEventCreateWithFlags(&h->mev[k], hipEventDisableTiming));
+    // all or nothing: a partial set is released and the step fails
+    std::vector<hipStream_t> st(h->count, nullptr);
+    std::vector<hipEvent_t> ev(h->count, nullptr);
+    hipEvent_t fork = nullptr;
+    bool ok = hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < h->count; ++k)
+      ok = hipStreamCreateWithFlags(&st[k], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      for (hipStream_t s : st)
+        if (s) (void)hipStreamDestroy(s);
+      for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+      if (fork) (void)hipEventDestroy(fork);
+      return fail(CAVITY_EHIP, "could not create the per-cavity streams");
     }
-    HIP_TRY(h, hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+    h->mst = st;
+    h->mev = ev;
+    h->fork_ev = fork;
   }
   HIP_TRY(h, hipEventRecord(h->fork_ev, h->st));
   for (int k = 0; k < h->count; ++k) HIP_TRY(h, hipStreamWaitEvent(h->mst[k], h->fork_ev, 0));
