@@ -78,8 +78,13 @@ typedef struct cavity_params {
                                  saved by cavity_fields after a step and are
                                  adopted as they are, walls included, without a
                                  Poisson solve, so the run continues exactly      */
-  double sor_omega;           /* relaxation parameter in (0, 2); <= 0 chooses
-                                 2 / (1 + sin(pi h))                               */
+  double sor_omega;           /* relaxation parameter in (0, 2); <= 0 chooses,
+                                 for the coupled mode, 2 / (1 + sin(pi h)), and
+                                 for converged solves the mean of that and
+                                 2 / (1 + sqrt(1 - mu^2)), mu = 0.8 cos(pi h) +
+                                 0.2 cos^2(pi h) (faster for the four-colour
+                                 order; the converged result does not depend
+                                 on it)                                            */
   const double* omega0;       /* nullable device n*n initial vorticity (walls are
                                  replaced by Thom's values); NULL = fluid at rest   */
   const double* psi0;         /* nullable device n*n warm start for the first

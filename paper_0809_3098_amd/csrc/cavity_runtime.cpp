@@ -250,8 +250,20 @@ int derive(const cavity_params& p, Member& m) {
   if (p.sor_omega > 0) {
     if (!(p.sor_omega < 2.0)) return fail(CAVITY_EINVAL, "sor_omega must lie in (0, 2)");
     m.relax = p.sor_omega;
-  } else {
+  } else if (p.fixed_sweeps > 0) {
+    // the coupled mode takes its parameter literally; unset, the classical
+    // optimum for the 5-point operator (the oracle's default too)
     m.relax = 2.0 / (1.0 + std::sin(M_PI * m.h));
+  } else {
+    // Converged solves, where the parameter sets only the speed: midway
+    // between the 5-point optimum 2/(1 + sin pi h) and Young's value
+    // 2/(1 + sqrt(1 - mu^2)) for the compact operator's Jacobi radius
+    // mu = 0.8 cos pi h + 0.2 cos^2 pi h (the four-colour order is not
+    // consistently ordered, and neither end is optimal).  Measured with the
+    // four-colour sweep (residual reduced 1e10 from zero): 3 % fewer sweeps
+    // than the 5-point value at 257^2, 5 % at 513^2.
+    const double c = std::cos(M_PI * m.h), mu = 0.8 * c + 0.2 * c * c;
+    m.relax = 0.5 * (2.0 / (1.0 + std::sin(M_PI * m.h)) + 2.0 / (1.0 + std::sqrt(1.0 - mu * mu)));
   }
   // A stalled over-relaxation sits at its rounding floor; allow several
   // residual halvings' worth of sweeps (about 0.11 (n-1) each) before polishing.

@@ -221,3 +221,34 @@ def test_residual_of_solution_is_at_rounding_level():
     r = poisson_residual(psi, omega, h)
     scale = np.max(np.abs(poisson_rhs(omega)))
     assert np.max(np.abs(r)) <= 1e-11 * scale
+
+
+def test_default_relaxation_beats_both_classical_values():
+    """The relaxation the library takes for converged solves, the mean of the
+    5-point optimum 2/(1 + sin pi h) and Young's value for the compact
+    operator's Jacobi radius mu = 0.8 cos pi h + 0.2 cos^2 pi h, needs fewer
+    four-colour sweeps to reduce the residual 1e10 than either of them (the
+    four-colour order of the 9-point stencil is not consistently ordered, so
+    neither classical value is optimal)."""
+    n = 65
+    h = mesh_spacing(n)
+    rng = np.random.default_rng(1)
+    omega = np.zeros((n, n))
+    omega[1:-1, 1:-1] = rng.standard_normal((n - 2, n - 2))
+    omega[-1, :] = -2.0 / h
+    c = np.cos(np.pi * h)
+    mu = 0.8 * c + 0.2 * c * c
+    w5 = 2.0 / (1.0 + np.sin(np.pi * h))
+    w9 = 2.0 / (1.0 + np.sqrt(1.0 - mu * mu))
+
+    def sweeps(relax):
+        p = np.zeros((n, n))
+        r0 = np.max(np.abs(poisson_residual(p, omega, h)))
+        for k in range(1, 5000):
+            p = sor_four_colour_sweep(p, omega, relax)
+            if np.max(np.abs(poisson_residual(p, omega, h))) <= 1e-10 * r0:
+                return k
+        return 5000
+
+    k5, k9, km = sweeps(w5), sweeps(w9), sweeps(0.5 * (w5 + w9))
+    assert km < k5 and km < k9, (km, k5, k9)
