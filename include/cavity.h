@@ -79,10 +79,10 @@ typedef struct cavity_params {
                                  adopted as they are, walls included, without a
                                  Poisson solve, so the run continues exactly      */
   double sor_omega;           /* relaxation parameter in (0, 2); <= 0 chooses,
-                                 for the coupled mode, 2 / (1 + sin(pi h)), and
-                                 for converged solves the mean of that and
-                                 2 / (1 + sqrt(1 - mu^2)), mu = 0.8 cos(pi h) +
-                                 0.2 cos^2(pi h) (faster for the four-colour
+                                 for the coupled mode, w5 = 2 / (1 + sin(pi h)),
+                                 and for converged solves w5 - 5/8 (w5 - w9),
+                                 w9 = 2 / (1 + sqrt(1 - mu^2)), mu = 0.8 cos(pi h)
+                                 + 0.2 cos^2(pi h) (faster for the four-colour
                                  order; the converged result does not depend
                                  on it)                                            */
   const double* omega0;       /* nullable device n*n initial vorticity (walls are
