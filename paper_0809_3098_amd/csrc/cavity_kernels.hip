@@ -516,10 +516,13 @@ __device__ __forceinline__ void tile_to_global(T* __restrict__ pout, int n, int 
         if (in0) coh_store(pout + g, pv[2 * cy][r]);
         if (in1) coh_store(pout + g + 1, pv[2 * cy + 1][r]);
       } else if (in0 && in1) {
-        T2 v;
+        // streaming store: the next launch reads psi from the memory side
+        // anyway, and the kernel's end then has fewer lines to write back
+        typedef T V2 __attribute__((ext_vector_type(2)));
+        V2 v;
         v.x = pv[2 * cy][r];
         v.y = pv[2 * cy + 1][r];
-        *reinterpret_cast<T2*>(pout + g) = v;
+        __builtin_nontemporal_store(v, reinterpret_cast<V2*>(pout + g));
       } else if (in0) {
         pout[g] = pv[2 * cy][r];
       } else if (in1) {
