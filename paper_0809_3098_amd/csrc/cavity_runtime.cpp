@@ -283,10 +283,10 @@ int derive(const cavity_params& p, Member& m) {
   // threads).  FP32 (no checking launches, so no wider halo): 88 x 56 tiles
   // with 5 sweeps at both sizes (2.38 / 20.0 us against 2.42 / 21.1 for the
   // next best).
-  if (p.n <= 320) {
-    m.cfg64 = {32, 32, 1, 256, 0};
-    m.cfg32 = {32, 32, 1, 256, 0};
-  } else if (p.n <= 2048) {
+  // Small grids take the same tiles: there the launch's fixed part dominates
+  // and five sweeps per launch amortise it, even with most CUs idle (129^2 to
+  // 320^2: 2.5-2.6 us per sweep against 5.3-5.9 for 32 x 32 tiles with one).
+  if (p.n <= 2048) {
     m.cfg64 = {84, 54, 5, 1024, 1};
     m.cfg32 = {88, 56, 5, 1024, 1};
   } else {
@@ -433,8 +433,10 @@ void carve(Member& m, char*& cur) {
 // overlap the other's sweeps (measured at 4096^2: 43.8 against 67.4 us per
 // FP64 sweep with 1024 threads).
 cav::SorConfig mg_cfg(int n) {
+  // up to 2048 nodes a side 64 x 32 tiles (3.1-3.4 us per sweep from 129^2 to
+  // 513^2 against 3.7-4.5 for 64 x 64 with 1024 threads or 32 x 32)
   if (n > 2048) return cav::SorConfig{64, 64, 2, 512, 0};
-  return n > 320 ? cav::SorConfig{64, 64, 2, 1024, 0} : cav::SorConfig{32, 32, 2, 256, 0};
+  return cav::SorConfig{64, 32, 2, 512, 0};
 }
 constexpr int kMgNu = 2;   // pre- and post-smoothing sweeps (one launch each)
 

@@ -34,10 +34,10 @@ def _inv_norm(n):
     return float(np.max(np.abs(poisson_solve(np.ones((n, n))))))
 
 
-# (n, sweeps): n <= 320 uses 32x32 tiles with 1 sweep per launch (pairs of 2),
-# larger n 84x54 tiles with 5 sweeps per launch (pairs of 10).
-@pytest.mark.parametrize("n,sweeps", [(5, 2), (33, 2), (64, 6), (97, 4), (330, 10), (400, 20),
-                                      (1024, 10)])
+# (n, sweeps): up to 2048 nodes a side the default tiles are 84 x 54 with 5
+# sweeps per launch (launch pairs of 10 sweeps)
+@pytest.mark.parametrize("n,sweeps", [(5, 10), (33, 10), (64, 20), (97, 10), (330, 10),
+                                      (400, 20), (1024, 10)])
 def test_fixed_sweeps_match_oracle_four_colour_sweeps(cav_mod, n, sweeps):
     print(f"[fixed sweeps] n={n} sweeps={sweeps}", flush=True)
     relax = 1.7
