@@ -9,10 +9,12 @@ Thom walls).  The headline workload is the 1024 x 1024 cavity at Re = 1e4,
 started from rest, FP64, Poisson tolerance 1e-10, solved by the paper's
 relaxation (four-colour SOR).  Inputs are resident in HBM when timing starts.
 Extras (same JSON line): the same workload with the multigrid solver and in
-persistent execution; the mixed-precision 1024 x 1024 Re = 3e4 cavity; the
-4096 x 4096 Re = 3e4 noise-start cavity (mixed SOR, and FP64 multigrid); the
-six-cavity Reynolds sweep (256^2 ... 1024^2) batched in one persistent launch
-per stage (hipGraph) vs the same cavities run one by one.  Prints one JSON line.
+persistent execution; the 1024 x 1024 Re = 3e4 cavity in FP64 and in mixed
+precision (same steps); the 4096 x 4096 Re = 3e4 noise-start cavity (FP64 SOR
+and mixed SOR for the same step, with the rooflines of both sweep kernels at
+that size, and FP64 multigrid); the six-cavity Reynolds sweep (256^2 ...
+1024^2) batched in one persistent launch per stage (hipGraph, tile shape from
+the autotuner) vs the same cavities run one by one.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -87,7 +89,19 @@ def _timed_steps(torch, cav, steps, warmup):
 
 
 def _sweep_roofline(torch, cav, stream, launches, arith, key):
-    """Average launch duration of the sweep kernel, event-timed on its stream."""
+    """Roofline of the sweep kernel, from its average launch duration
+    event-timed on the stream it runs on.
+
+    A launch of S sweeps must move psi in, F in and psi out once (24 B per
+    interior node in FP64, 12 B in FP32): those bytes over the launch time,
+    against the 8 TB/s HBM peak, are ``achieved`` and ``frac``.  ``effective``
+    counts 24 (12) B per node for each of the S sweeps, the per-sweep figure
+    of a stencil sweep that reads and writes every field once; it exceeds what
+    a launch moves because the S sweeps run on chip.  ``traffic`` is the
+    L2-miss bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by the same
+    counters of a 1 GiB copy) from the committed counter record of this
+    kernel source, else null; at 1024^2 these are mostly served by the
+    Infinity Cache, at 4096^2 by HBM."""
     tun = cav.tuning(0)
     s = tun["sweeps_per_launch32"] if arith else tun["sweeps_per_launch"]
     n = cav.params[0].n
@@ -99,15 +113,28 @@ def _sweep_roofline(torch, cav, stream, launches, arith, key):
     ev1.record(stream)
     ev1.synchronize()
     per_launch_s = ev0.elapsed_time(ev1) / 1e3 / (done // s)
-    alg = BYTES_PER_SWEEP_NODE[arith] * (n - 2) ** 2 * s
-    achieved = alg / per_launch_s / 1e9
+    moved = BYTES_PER_SWEEP_NODE[arith] * (n - 2) ** 2
+    achieved = moved / per_launch_s / 1e9
+    eff = moved * s / per_launch_s / 1e9
     if arith:
         kern = f"k_sor<float,{tun['tile_x32']},{tun['tile_y32']},{s},{tun['threads32']}>"
     else:
         kern = f"k_sor<double,{tun['tile_x']},{tun['tile_y']},{s},{tun['threads']}>"
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(key), "kernel": kern,
-            "alg_bytes_per_launch": alg, "avg_launch_us": round(per_launch_s * 1e6, 3)}
+    traffic = _traffic(key)
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "traffic_kind": "L2-miss bytes per launch (Infinity Cache and HBM), rocprofv3 "
+                           "FETCH_SIZE + WRITE_SIZE scaled by a 1 GiB copy",
+           "kernel": kern, "n": n, "sweeps_per_launch": s, "bytes_per_launch": moved,
+           "avg_launch_us": round(per_launch_s * 1e6, 3),
+           "effective": {"bytes_per_launch": moved * s, "gbs": round(eff, 1),
+                         "frac": round(eff / HBM_PEAK_GBS, 4),
+                         "per": f"{int(BYTES_PER_SWEEP_NODE[arith])} B per node for each of "
+                                f"the {s} sweeps of a launch"}}
+    if traffic:
+        out["traffic_gbs"] = round(traffic / per_launch_s / 1e9, 1)
+        out["traffic_frac"] = round(traffic / per_launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def main():
@@ -117,6 +144,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cavity1024_re1e4_fp64")
     ap.add_argument("--exec", default="stream", choices=sorted(EXEC))
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="override the workload's precision (the headline run only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed and batched lines")
     ap.add_argument("--cpu-steps", type=int, default=150)
@@ -125,6 +154,8 @@ def main():
                     help="end with a cold 1 GiB device copy (torch), the known-size kernel the "
                          "HBM counters of a profiling run are scaled by")
     ap.add_argument("--extra-steps", type=int, default=5)
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON-lines cache of the autotuner (default: none, tune every run)")
     ap.add_argument("--log-run", default=None, metavar="JSONL",
                     help="instead of the bench: run the 4096^2 Re 3e4 noise-start cavity "
                          "(mixed, multigrid) for --log-steps steps, one monitor line per step")
@@ -248,11 +279,17 @@ def main():
         return cav, prec, out
 
     # ---- headline: FP64 1024^2
-    cav, prec, head = single(args.workload, args.steps, args.warmup, args.exec)
+    prec_override = None if args.precision is None else (
+        CAVITY_MIXED if args.precision == "mixed" else CAVITY_FP64)
+    cav, prec, head = single(args.workload, args.steps, args.warmup, args.exec,
+                             precision=prec_override)
     wl = WORKLOADS[args.workload]
     n = wl["n"]
     roofline = _sweep_roofline(torch, cav, stream, args.relax_launches, 0,
                                f"{args.workload}:fp64")
+    if prec == CAVITY_MIXED:
+        head["roofline_fp32_sweep"] = _sweep_roofline(torch, cav, stream, args.relax_launches, 1,
+                                                      f"{args.workload}:fp32")
     cav.close()
 
     extras = {}
@@ -274,18 +311,39 @@ def main():
             cs_, _, strm = single(args.workload, args.steps, args.warmup, "stream")
             cs_.close()
             extras["stream_1024_re1e4_fp64"] = strm
-        # mixed + refinement at 1024^2, Re 3e4
+        # FP64 and mixed + refinement on the same workload (1024^2, Re 3e4), with the
+        # same steps and warm-up
+        c64, _, r64 = single("cavity1024_re3e4_mixed", args.extra_steps, 1, args.exec,
+                             precision=CAVITY_FP64)
+        c64.close()
+        extras["sor_fp64_1024_re3e4"] = r64
         cavm, _, mixed = single("cavity1024_re3e4_mixed", args.extra_steps, 1, args.exec)
         mixed["roofline_fp32_sweep"] = _sweep_roofline(torch, cavm, stream, args.relax_launches,
                                                        1, "cavity1024_re3e4_mixed:fp32")
+        mixed["speedup_vs_fp64_same_workload"] = round(mixed["value"] / r64["value"], 3)
         cavm.close()
         extras["mixed_1024_re3e4"] = mixed
-        # 4096^2, Re 3e4, noise start: mixed SOR (the configuration) and FP64 multigrid
-        c4, _, m4 = single("cavity4096_re3e4_mixed_noise", 1, 0, "stream")
+        # 4096^2, Re 3e4, noise start (the HBM-resident case): FP64 SOR and mixed SOR for
+        # the same first step, the rooflines of both sweep kernels at this size, and FP64
+        # multigrid
+        key4 = "cavity4096_re3e4_mixed_noise"
+        c4, _, f4 = single(key4, 1, 0, "stream", precision=CAVITY_FP64)
+        f4["roofline_fp64_sweep"] = _sweep_roofline(torch, c4, stream, 40, 0, f"{key4}:fp64")
+        c4.close()
+        extras["cavity4096_re3e4_noise_fp64_sor"] = f4
+        c4, _, m4 = single(key4, 1, 0, "stream")
+        m4["roofline_fp32_sweep"] = _sweep_roofline(torch, c4, stream, 40, 1, f"{key4}:fp32")
+        m4["speedup_vs_fp64_same_workload"] = round(m4["value"] / f4["value"], 3)
         c4.close()
         extras["cavity4096_re3e4_noise_mixed_sor"] = m4
-        c4, _, g4 = single("cavity4096_re3e4_mixed_noise", args.extra_steps, 1, "stream",
-                           CAVITY_SOLVER_MG, CAVITY_FP64)
+        # per-step cross-check of the 4096^2 sweep rooflines: the bytes every sweep
+        # launch of a step must move, over the whole step's time (all kernels)
+        for rec, key in ((f4, "roofline_fp64_sweep"), (m4, "roofline_fp32_sweep")):
+            rl = rec[key]
+            launches = 5 * rec["sweeps_per_stage"] / rl["sweeps_per_launch"]
+            rl["per_step_gbs"] = round(launches * rl["bytes_per_launch"] /
+                                       (rec["ms_per_step"] / 1e3) / 1e9, 1)
+        c4, _, g4 = single(key4, args.extra_steps, 1, "stream", CAVITY_SOLVER_MG, CAVITY_FP64)
         c4.close()
         extras["cavity4096_re3e4_noise_fp64_multigrid"] = g4
         # coupled mode: a fixed 20 sweeps per stage with beta = 0.8 (no stopping test)
@@ -308,6 +366,8 @@ def main():
                          for r, m in b["members"]], device="cuda:0", stream=stream)
             default_exec = cb.exec_mode()
             cb.set_exec(EXEC["graph"])
+            # the persistent kernel's tile shape chosen by the autotuner (timed rounds)
+            tuned = cb.autotune(-1, args.tune_cache)
             el, _ = _timed_steps(torch, cb, args.extra_steps, 1)
             cb.close()
             # the same batch in stream execution: one stream per cavity
@@ -330,6 +390,10 @@ def main():
                 "sequential_stream_mcell_steps_s": round(cells * args.extra_steps / seq / 1e6, 4),
                 "speedup": round(seq / el, 3), "speedup_streams": round(seq / el_st, 3),
                 "default_exec": {v: k for k, v in EXEC.items()}[default_exec],
+                "graph_tuning": {k: tuned[k] for k in ("tile_x", "tile_y", "sweeps_per_launch",
+                                                       "threads", "tile_x32", "tile_y32",
+                                                       "sweeps_per_launch32", "threads32",
+                                                       "check_every", "inner_sweeps")},
                 "steps": args.extra_steps}
 
     cpu = None if args.no_cpu else _cpu_baseline(n, wl["re"], args.cpu_steps)
@@ -339,10 +403,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == CAVITY_FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "re": wl["re"], "poisson_tol": wl["tol"],
-                   "precision": wl["precision"], "init": wl["init"], "exec": head["exec"],
+                   "precision": head["precision"], "init": wl["init"], "exec": head["exec"],
                    "sweeps_per_stage": head["sweeps_per_stage"],
                    "floor_limited_last_step": head["floor_limited_last_step"]},
         "roofline": roofline,
+        **({"roofline_fp32_sweep": head["roofline_fp32_sweep"]}
+           if "roofline_fp32_sweep" in head else {}),
         "cpu_baseline": cpu,
         "extras": extras,
     }

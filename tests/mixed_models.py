@@ -1,0 +1,130 @@
+"""Test-side precision models of the mixed-precision time step.
+
+Two subclasses of the FP64 oracle, used only to set the tolerances of the
+mixed-precision GPU tests (nothing here is part of the oracle):
+
+* ``MixedModel`` -- the precision design: the transport right-hand side of
+  eq. (Lwn) is evaluated in FP32 from psi and omega rounded to FP32; the
+  SSPRK stage combination (eqs. SSPRK54_1-5), the Poisson solve and Thom's
+  wall formula stay FP64.  Its error against the FP64 oracle is the error the
+  design itself allows.
+* ``Fp32OmegaModel`` -- a defective variant: as above, but every stage's
+  vorticity (interior combination and the walls Thom writes) is stored in
+  FP32.  A mixed-precision tolerance has discriminating power when it rejects
+  this run.
+
+``mixed_tolerances`` runs the FP64 oracle and both models on one workload and
+returns tolerances of ``FACTOR`` times the design's error for psi, omega and
+the kinetic energy, together with the defective run's errors, so a test can
+assert that the tolerance rejects the defective run while the HIP path
+passes.  The three runs are independent and go to threads (NumPy and
+scipy.fft release the interpreter lock in their array loops).
+"""
+from __future__ import annotations
+
+import functools
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+from oracle.cavity_oracle import CavityOracle, transport_rhs
+
+#: Tolerance = FACTOR x the error of the precision design's model.  The GPU
+#: rounds differently (fused multiply-adds, its own operation order), so its
+#: error is a different draw of the same rounding noise; 3 covers that while
+#: staying below the defective run's error on the workloads the tests use.
+FACTOR = 3.0
+#: FP64-level floor added to every tolerance (the design's error is never
+#: below what the FP64 path itself may differ by).
+FLOOR = 1e-11
+
+
+class MixedModel(CavityOracle):
+    """L(omega) of eq. (Lwn) in FP32 arithmetic from FP32-rounded psi and omega."""
+
+    def _rhs(self, state):
+        omega, psi = state
+        L = transport_rhs(omega.astype(np.float32), psi.astype(np.float32),
+                          np.float32(self.h), np.float32(self.nu))
+        assert L.dtype == np.float32
+        return L.astype(np.float64)
+
+
+class Fp32OmegaModel(MixedModel):
+    """MixedModel with every stage's vorticity stored in FP32 (a defect)."""
+
+    @staticmethod
+    def _combine(ys, ks):
+        return MixedModel._combine(ys, ks).astype(np.float32).astype(np.float64)
+
+    def _finish(self, omega_new, state_in):
+        w, psi = super()._finish(omega_new, state_in)
+        return (w.astype(np.float32).astype(np.float64), psi)
+
+
+def rel(a, b):
+    """max |a - b| / max |b|."""
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _run(cls, n, re, steps, omega0, dt, interior):
+    o = cls(n, re, omega0=omega0, dt=dt, workers=-1)
+    d = o.step(steps, diagnostics_every=steps)
+    psi, omega = o.psi, o.omega
+    if interior:
+        k = interior
+        psi, omega = psi[k:-k, k:-k], omega[k:-k, k:-k]
+    return psi, omega, d["ke"]
+
+
+def _errors(run, ref):
+    return {"psi": rel(run[0], ref[0]), "omega": rel(run[1], ref[1]),
+            "ke": abs(run[2] - ref[2]) / abs(ref[2])}
+
+
+@functools.lru_cache(maxsize=None)
+def _developed(n, re, steps):
+    o = CavityOracle(n, re, workers=-1)
+    o.step(steps)
+    return o.omega
+
+
+def initial_omega(n, re, init_key):
+    """omega0 of a workload: None (rest), ("noise", amplitude, seed) or
+    ("developed", steps): the FP64 oracle's vorticity after that many steps
+    from rest at cfl 0.5 (walls included), a flow with every term of
+    eq. (Lwn) active."""
+    if init_key is None:
+        return None
+    if init_key[0] == "noise":
+        from paper_0809_3098_amd import inputs
+        return inputs.noise_omega0(n, init_key[1], init_key[2])
+    assert init_key[0] == "developed"
+    return _developed(n, re, init_key[1]).copy()
+
+
+@functools.lru_cache(maxsize=None)
+def _cached(n, re, steps, init_key, dt, interior):
+    omega0 = initial_omega(n, re, init_key)
+    with ThreadPoolExecutor(max_workers=3) as ex:
+        futs = [ex.submit(_run, cls, n, re, steps, omega0, dt, interior)
+                for cls in (CavityOracle, MixedModel, Fp32OmegaModel)]
+        ref, model, bad = (f.result() for f in futs)
+    return ref, _errors(model, ref), _errors(bad, ref)
+
+
+def mixed_tolerances(n, re, steps, init_key=None, dt=None, interior=0):
+    """(reference fields, tolerances, design errors, defective-run errors).
+
+    reference = (psi, omega, ke) of the FP64 oracle (cropped to nodes at least
+    ``interior`` from every wall when ``interior`` > 0).  Tolerances are
+    FACTOR x the design's errors plus FLOOR, per quantity.
+    """
+    ref, model, bad = _cached(n, re, steps, init_key, dt, interior)
+    tol = {k: FACTOR * v + FLOOR for k, v in model.items()}
+    return ref, tol, model, bad
+
+
+def rejects(tol, errs, keys=("psi", "omega", "ke")):
+    """Whether a check 'every error within its tolerance' fails for errs."""
+    return any(errs[k] > tol[k] for k in keys)

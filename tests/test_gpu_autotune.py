@@ -6,6 +6,7 @@ import os
 import numpy as np
 import pytest
 
+from mixed_models import mixed_tolerances, rejects, rel
 from oracle.cavity_oracle import CavityOracle
 
 pytestmark = pytest.mark.gpu
@@ -62,8 +63,16 @@ def test_autotune_mixed_and_batch(cm, tmp_path, precision):
     assert all(s["status"] == 0 and s["step"] == 4 for s in st)
     psi, omega, _, _ = c.fields(0)
     c.close()
-    ref = CavityOracle(128, 5000.0)
-    ref.step(4)
-    ep = np.max(np.abs(psi - ref.psi)) / np.max(np.abs(ref.psi))
-    bound = 1e-11 if precision == 0 else 1e-6
-    assert ep <= bound, ep
+    if precision == 0:
+        ref = CavityOracle(128, 5000.0)
+        ref.step(4)
+        ep, ew = rel(psi, ref.psi), rel(omega, ref.omega)
+        assert ep <= 1e-11 and ew <= 1e-11, (ep, ew)
+    else:
+        # the precision design's tolerances (see test_gpu_mixed), which reject
+        # a run that stores omega in FP32
+        (rpsi, romega, _), tol, _, bad = mixed_tolerances(128, 5000.0, 4)
+        ep, ew = rel(psi, rpsi), rel(omega, romega)
+        print(f"  psi {ep:.3e} (tol {tol['psi']:.3e}) omega {ew:.3e} (tol {tol['omega']:.3e})")
+        assert rejects(tol, bad, ("psi", "omega"))
+        assert ep <= tol["psi"] and ew <= tol["omega"], (ep, ew, tol)

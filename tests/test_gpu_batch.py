@@ -13,6 +13,10 @@ from oracle.cavity_oracle import CavityOracle
 
 pytestmark = pytest.mark.gpu
 
+SMALL4 = [(5000.0, 130), (10000.0, 257), (15000.0, 384), (20000.0, 512)]
+SWEEP6 = [(5000.0, 256), (10000.0, 512), (15000.0, 768), (20000.0, 1024), (25000.0, 1024),
+          (30000.0, 1024)]
+
 
 @pytest.fixture(scope="module")
 def cm():
@@ -62,8 +66,7 @@ def test_batch_bitwise_equals_solo_runs(cm, mode, precision):
 
 def test_reynolds_sweep_six_cavities_graph(cm):
     """The six-cavity Reynolds sweep (256^2 ... 1024^2) in graph mode."""
-    members = [(5000.0, 256), (10000.0, 512), (15000.0, 768), (20000.0, 1024),
-               (25000.0, 1024), (30000.0, 1024)]
+    members = SWEEP6
     steps = 3
     print("[re sweep] six cavities", flush=True)
     c = cm.Cavity([cm.Params(n=n, re=re) for re, n in members])
@@ -79,10 +82,57 @@ def test_reynolds_sweep_six_cavities_graph(cm):
         assert np.all(psi[0, :] == 0) and np.all(psi[-1, :] == 0)
         assert np.all(psi[:, 0] == 0) and np.all(psi[:, -1] == 0)
         assert np.all(np.isfinite(omega))
-    # the smallest member against the oracle
-    ref = CavityOracle(256, 5000.0, workers=-1)
-    ref.step(steps)
-    ep = np.max(np.abs(fields[0][0] - ref.psi)) / np.max(np.abs(ref.psi))
-    ew = np.max(np.abs(fields[0][1] - ref.omega)) / np.max(np.abs(ref.omega))
-    print(f"  256^2 member: psi_rel={ep:.3e} omega_rel={ew:.3e}")
-    assert ep <= 1e-11 and ew <= 1e-11
+    # every member against the oracle
+    for k, (re, n) in enumerate(members):
+        ref = CavityOracle(n, re, workers=-1)
+        ref.step(steps)
+        ep = np.max(np.abs(fields[k][0] - ref.psi)) / np.max(np.abs(ref.psi))
+        ew = np.max(np.abs(fields[k][1] - ref.omega)) / np.max(np.abs(ref.omega))
+        print(f"  {n}^2 Re {re:g}: psi_rel={ep:.3e} omega_rel={ew:.3e}")
+        assert ep <= 1e-11 and ew <= 1e-11, (k, ep, ew)
+
+
+@pytest.mark.parametrize("members,mode", [(SMALL4, "persistent"), (SMALL4, "graph"),
+                                          (SWEEP6, "graph")])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_default_tuning_bitwise_equals_solo(cm, members, mode, precision):
+    """The batch's own default tuning (tiles, sweeps per round, check spacing,
+    FP32 rounds), each member stopping on its own: on cavities of 130 to 512
+    nodes a side (64 x 32 tiles, four sweeps per round) and on the six-cavity
+    Reynolds sweep (64 x 64 tiles; 992 tiles, more than the co-resident grid,
+    so blocks take several tiles per round), every step of every member
+    equals the same cavity run alone with the same sweep schedule, bitwise."""
+    steps = 3
+    print(f"[batch default {mode} precision={precision}] {members}", flush=True)
+    c = cm.Cavity([cm.Params(n=n, re=re, precision=precision) for re, n in members])
+    c.set_exec(cm.CAVITY_EXEC_PERSISTENT if mode == "persistent" else cm.CAVITY_EXEC_GRAPH)
+    bt = c.tuning(-1)
+    tiles = sum(((n + bt["tile_x"] - 1) // bt["tile_x"]) * ((n + bt["tile_y"] - 1) // bt["tile_y"])
+                for _, n in members)
+    print(f"  batch tuning {bt}, {tiles} FP64 tiles")
+    solos = []
+    for re, n in members:
+        s = cm.Cavity(cm.Params(n=n, re=re, precision=precision))
+        t = s.tuning()
+        # the results do not depend on the tile shape, only on the sweeps per
+        # check (FP64) or per refinement round (mixed) and the relaxation
+        s.set_tuning(tile_x=64, tile_y=64, sweeps_per_launch=bt["sweeps_per_launch"],
+                     threads=512 if bt["sweeps_per_launch"] == 4 else 1024,
+                     tile_x32=bt["tile_x32"], tile_y32=bt["tile_y32"],
+                     sweeps_per_launch32=bt["sweeps_per_launch32"], threads32=bt["threads32"],
+                     check_every=bt["check_every"], inner_sweeps=bt["inner_sweeps"],
+                     sor_omega=t["sor_omega"])
+        solos.append(s)
+    for step in range(steps):
+        stats = c.step(1)
+        for k, solo in enumerate(solos):
+            st = solo.step(1)[0]
+            p, w, _, _ = solo.fields()
+            gp, gw, _, _ = c.fields(k)
+            assert np.array_equal(gp, p), (step, k)
+            assert np.array_equal(gw, w), (step, k)
+            assert stats[k]["sweeps_last_step"] == st["sweeps_last_step"], (step, k)
+            assert stats[k]["status"] == 0
+    c.close()
+    for solo in solos:
+        solo.close()

@@ -6,7 +6,12 @@
   leave an error of ||A^-1|| * tol in psi, so the comparison uses that bound
   (||A^-1||_inf computed by the oracle, the residual reported by the GPU);
   omega inherits the psi error through Thom's wall formula (2 / h^2), and the
-  mixed path adds its FP32 bound of eq. (Lwn) terms.
+  mixed path adds 3 times the error of the precision design's CPU model
+  (``mixed_models.MixedModel``: eq. (Lwn) in FP32) for psi and omega.  Here
+  the solver-tolerance term through Thom's 2 / h^2 (about 1e-3) exceeds what
+  storing omega in FP32 would cost (about 4e-4), so this one-step check
+  cannot see that defect; the mixed tests with discriminating tolerances are
+  in test_gpu_mixed (including the 1024^2 cavity).
 * The largest grid the library accepts (16385 x 16385): a solve stopped by
   its sweep limit is checked at sample nodes -- centre, next to a wall, next
   to a corner -- against the oracle's four-colour sweeps on a window around
@@ -15,12 +20,11 @@
 import numpy as np
 import pytest
 
-from oracle.cavity_oracle import CavityOracle, poisson_solve, sor_four_colour_sweep, transport_rhs
+from mixed_models import FACTOR, mixed_tolerances
+from oracle.cavity_oracle import CavityOracle, poisson_solve, sor_four_colour_sweep
 from paper_0809_3098_amd import inputs
 
 pytestmark = pytest.mark.gpu
-
-EPS32 = float(np.finfo(np.float32).eps)
 
 
 @pytest.fixture(scope="module")
@@ -51,9 +55,9 @@ def _run(cm, n, re, w0, precision, solver):
     return psi, omega, st
 
 
-def _check(psi, omega, ref, inv, resid, extra_w=0.0):
+def _check(psi, omega, ref, inv, resid, extra_w=0.0, extra_psi=0.0):
     h = ref.h
-    bpsi = 5.5 * inv * resid + 1e-14 * np.max(np.abs(ref.psi))
+    bpsi = 5.5 * inv * resid + 1e-14 * np.max(np.abs(ref.psi)) + extra_psi
     bw = 2.0 / (h * h) * bpsi + extra_w + 1e-12 * np.max(np.abs(ref.omega))
     ep = np.max(np.abs(psi - ref.psi))
     ew = np.max(np.abs(omega - ref.omega))
@@ -74,12 +78,10 @@ def test_cavity4096_one_step_mixed_sor(cm, ref4096):
     print(f"[4096 mixed sor] n={n} re={re}", flush=True)
     psi, omega, st = _run(cm, n, re, w0, cm.CAVITY_MIXED, 0)
     assert st["status"] == 0
-    # FP32 evaluation of eq. (Lwn): a few roundings of its largest term per
-    # stage (the bound of the mixed-precision tests), over one step
-    term = float(np.max(np.abs(transport_rhs(ref.omega, ref.psi, ref.h, ref.nu))))
-    lap = ref.nu * 8.0 * np.max(np.abs(ref.omega)) / ref.h ** 2
-    extra = 5 * ref.dt * 8 * EPS32 * max(term, lap)
-    _check(psi, omega, ref, inv, 1e-10, extra)
+    _, _, model, _ = mixed_tolerances(n, re, 1, ("noise", 1e-3, 0))
+    extra_psi = FACTOR * model["psi"] * np.max(np.abs(ref.psi))
+    extra_w = FACTOR * model["omega"] * np.max(np.abs(ref.omega))
+    _check(psi, omega, ref, inv, 1e-10, extra_w, extra_psi)
 
 
 def test_largest_grid_sampled_sweeps(cm):

@@ -9,6 +9,7 @@ coarsening; n = 65, 257 are nested throughout.
 import numpy as np
 import pytest
 
+from mixed_models import mixed_tolerances, rejects, rel
 from oracle.cavity_oracle import CavityOracle, poisson_solve
 from paper_0809_3098_amd import inputs
 
@@ -105,12 +106,10 @@ def test_mixed_multigrid_step_error(cm):
     st = c.step(steps)[0]
     psi, omega, _, _ = c.fields()
     c.close()
-    ref = CavityOracle(n, re)
-    d = ref.step(steps, diagnostics_every=steps)
-    ep = np.max(np.abs(psi - ref.psi)) / np.max(np.abs(ref.psi))
-    ew = np.max(np.abs(omega - ref.omega)) / np.max(np.abs(ref.omega))
-    ek = abs(st["ke"] - d["ke"]) / d["ke"]
-    print(f"  psi_rel={ep:.3e} omega_rel={ew:.3e} ke_rel={ek:.3e}")
-    # the FP32 transport stencil bounds these (see test_gpu_mixed); multigrid
-    # changes nothing there
-    assert max(ep, ew, ek) <= 1e-6
+    # the FP32 transport stencil sets the error (see test_gpu_mixed); the
+    # solver changes nothing there, so the same model tolerances apply
+    (rpsi, romega, rke), tol, model, bad = mixed_tolerances(n, re, steps)
+    err = {"psi": rel(psi, rpsi), "omega": rel(omega, romega), "ke": abs(st["ke"] - rke) / rke}
+    print(f"  errors {err} tolerances {tol} fp32-omega run {bad}")
+    assert rejects(tol, bad)
+    assert all(err[k] <= tol[k] for k in err), (err, tol)

@@ -13,6 +13,7 @@ tiles kept on chip, halos swapped with the neighbouring tiles every round.
 import numpy as np
 import pytest
 
+from mixed_models import mixed_tolerances, rejects
 from oracle.cavity_oracle import CavityOracle, poisson_solve, sor_four_colour_sweep
 from paper_0809_3098_amd import inputs
 
@@ -95,13 +96,19 @@ def test_resident_steps_match_oracle_and_stream(cm, n, re, steps):
 
 def test_resident_mode_runs_other_cavities_as_stream(cm):
     print("[resident fallback]", flush=True)
-    members = [cm.Params(n=130, re=2000.0), cm.Params(n=130, re=2000.0, precision=cm.CAVITY_MIXED)]
+    n, re, steps = 130, 2.0e4, 5
+    members = [cm.Params(n=n, re=re), cm.Params(n=n, re=re, precision=cm.CAVITY_MIXED)]
     c = cm.Cavity(members)
     c.set_exec(cm.CAVITY_EXEC_RESIDENT)
     assert c.exec_mode() == cm.CAVITY_EXEC_RESIDENT
-    stats = c.step(5)
+    stats = c.step(steps)
     assert all(s["status"] == 0 for s in stats)
-    p64 = c.fields(0)[0]
-    p32 = c.fields(1)[0]
+    p64, w64 = c.fields(0)[:2]
+    p32, w32 = c.fields(1)[:2]
     c.close()
-    assert _rel(p32, p64) <= 1e-6
+    # the FP64 cavity (resident) at parity, the mixed one (per launch) within
+    # the precision design's tolerances (see test_gpu_mixed)
+    (rpsi, romega, _), tol, _, bad = mixed_tolerances(n, re, steps)
+    assert _rel(p64, rpsi) <= PARITY and _rel(w64, romega) <= PARITY
+    assert rejects(tol, bad, ("psi", "omega"))
+    assert _rel(p32, rpsi) <= tol["psi"] and _rel(w32, romega) <= tol["omega"]

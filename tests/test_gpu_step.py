@@ -71,6 +71,21 @@ def test_step_parity_1024_after_100_steps(cm):
     assert ep <= PARITY and ew <= PARITY, (ep, ew)
 
 
+def test_step_parity_1024_paper_time_step(cm):
+    """The time step of the paper's production runs (Sec. 4, Table tab:grid):
+    dt = 0.001 at 1024^2, a Courant number of 1.02 against 0.5 elsewhere."""
+    n, re, steps, dt = 1024, 1.0e4, 100, 1e-3
+    print(f"[step parity] n={n} re={re} steps={steps} dt={dt}", flush=True)
+    (psi, omega, _, _), st = _run_gpu(cm, n, re, steps, dt=dt, poisson_tol=1e-10)
+    ref = CavityOracle(n, re, dt=dt, workers=-1)
+    ref.step(steps)
+    ep, ew = _rel(psi, ref.psi), _rel(omega, ref.omega)
+    print(f"  psi_rel={ep:.3e} omega_rel={ew:.3e} sweeps/step={st['sweeps_last_step']} "
+          f"floor={st['floor_limited']}")
+    assert st["status"] == 0
+    assert ep <= PARITY and ew <= PARITY, (ep, ew)
+
+
 def test_walls_zero_and_bitwise_repeatable(cm):
     n, re, steps = 130, 3000.0, 15
     print(f"[repeatable] n={n}", flush=True)
