@@ -26,6 +26,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -163,6 +165,15 @@ def main():
     ap.add_argument("--grid-study", default=None, metavar="JSONL",
                     help="instead of the bench: run the coarse-grid cavities of the grid "
                          "dependence study towards a steady state, one line per chunk")
+    ap.add_argument("--study-workload", default="grid_dependence",
+                    help="workload of --grid-study: grid_dependence (220^2, 300^2), "
+                         "grid_dependence_1024, steady_table_1024 (Sec. 4 production runs)")
+    ap.add_argument("--study-members", default=None,
+                    help="comma-separated indices of the workload's members to run")
+    ap.add_argument("--checkpoint", default=None, metavar="DIR",
+                    help="save each cavity's psi, omega and step count there at its end")
+    ap.add_argument("--resume", default=None, metavar="DIR",
+                    help="continue each cavity from its state saved there (if any)")
     ap.add_argument("--study-steps", type=int, default=200000)
     ap.add_argument("--study-chunk", type=int, default=1000)
     ap.add_argument("--study-seconds", type=float, default=240.0,
@@ -209,44 +220,67 @@ def main():
         # one handle per cavity, so that a cavity whose run blows up (a possible
         # outcome on a coarse grid) ends only its own run
         from paper_0809_3098_amd.cavity import CAVITY_ENONFINITE, CavityError
-        wl = WORKLOADS["grid_dependence"]
-        with open(args.grid_study, "w") as f:
-            for r, m in wl["members"]:
-                cav = Cavity(Params(n=m, re=r, dt=wl["dt"], poisson_tol=wl["tol"]),
-                             device="cuda:0", stream=stream)
+        wl = WORKLOADS[args.study_workload]
+        members = wl["members"]
+        if args.study_members:
+            members = [members[int(k)] for k in args.study_members.split(",")]
+        with open(args.grid_study, "a" if args.resume else "w") as f:
+            for r, m in members:
+                tag = f"n{m}_re{int(r)}"
+                resume = None
+                if args.resume:
+                    # a state saved by an earlier run of this cavity: psi and omega
+                    # after `step` steps, adopted as they are (cavity_create resume=1)
+                    path = os.path.join(args.resume, f"{tag}.npz")
+                    if os.path.exists(path):
+                        resume = np.load(path)
+                base = int(resume["step"]) if resume is not None else 0
+                cav = Cavity(Params(n=m, re=r, dt=wl["dt"], poisson_tol=wl["tol"],
+                                    resume=1 if resume is not None else 0),
+                             device="cuda:0", stream=stream,
+                             omega0=[resume["omega"]] if resume is not None else None,
+                             psi0=[resume["psi"]] if resume is not None else None)
                 # the multigrid solver reaches the same discrete solution with far
-                # fewer launches per stage than SOR on these small grids
+                # fewer launches per stage than SOR
                 cav.set_tuning(solver=CAVITY_SOLVER_MG)
                 t0 = time.perf_counter()
                 done, first, outcome = 0, -1, "max_steps"
-                while done < args.study_steps:
-                    chunk = min(args.study_chunk, args.study_steps - done)
+                while base + done < args.study_steps:
+                    chunk = min(args.study_chunk, args.study_steps - base - done)
                     try:
                         steady, stats = cav.run_steady(chunk, 100)
                     except CavityError as e:
                         if e.code != CAVITY_ENONFINITE:
                             raise
-                        outcome = f"non-finite after step {done}"
+                        outcome = f"non-finite after step {base + done}"
                         break
                     st = stats[0]
                     done = st["step"]
-                    rec = {"n": m, "re": r, "step": done, "t": round(st["t"], 6),
+                    rec = {"n": m, "re": r, "step": base + done,
+                           "t": round((base + done) * wl["dt"], 6),
                            "wall_s": round(time.perf_counter() - t0, 2),
                            "res_psi": st["res_psi"], "res_omega": st["res_omega"],
                            "ke": st["ke"], "domega_inf_over_dt": st["domega_inf_over_dt"],
-                           "sweeps_last_step": st["sweeps_last_step"], "steady_step": steady[0]}
+                           "sweeps_last_step": st["sweeps_last_step"],
+                           "steady_step": steady[0] + base if steady[0] >= 0 else -1}
                     f.write(json.dumps(rec) + "\n")
                     f.flush()
                     print(json.dumps(rec), flush=True)
                     if steady[0] >= 0:
-                        first, outcome = steady[0], "steady"
+                        first, outcome = steady[0] + base, "steady"
                         break
                     if time.perf_counter() - t0 > args.study_seconds:
                         outcome = "time limit"
                         break
+                if args.checkpoint:
+                    os.makedirs(args.checkpoint, exist_ok=True)
+                    psi, omega = cav.fields()[:2]
+                    np.savez(os.path.join(args.checkpoint, f"{tag}.npz"), psi=psi, omega=omega,
+                             step=base + done)
                 summary = {"n": m, "re": r, "dt": wl["dt"], "solver": "multigrid",
                            "outcome": outcome, "steady_step": first,
-                           "steps": done, "t": round(done * wl["dt"], 6),
+                           "steps": base + done, "t": round((base + done) * wl["dt"], 6),
+                           "resumed_from_step": base,
                            "wall_s": round(time.perf_counter() - t0, 2)}
                 f.write(json.dumps({"summary": summary}) + "\n")
                 print(json.dumps({"summary": summary}), flush=True)

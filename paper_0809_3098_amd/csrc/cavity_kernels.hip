@@ -182,6 +182,66 @@ template <typename T> struct Pair;
 template <> struct Pair<double> { using type = double2; };
 template <> struct Pair<float> { using type = float2; };
 
+// The relaxation target of eq. (SequationFinal) in correction form for one
+// node of x-parity CX (see the sweep comment above):
+//   g = 0.2 (E + W + N + S) + 0.05 (NE + NW + SE + SW) + F.
+// Its E / W and diagonal neighbours come in pairs: one node in this lane
+// (e, dn, ds) and one in the adjacent lane, which holds the same kind of node
+// for its own column.  So the lane's share
+//   q = e + 0.25 (dn + ds)
+// and the adjacent lane's q, fetched by one wavefront shift, give
+//   g = 0.2 ((q + q_adjacent) + (sn + ss)) + F,
+// the same sum (0.25 = 0.05 / 0.2 is exact) with one shifted value per node
+// instead of three.  For CX = 0 the other-side column is the left lane's, for
+// CX = 1 the right lane's.
+template <int CX, typename T>
+__device__ __forceinline__ T gs_target(T e, T sn, T ss, T dn, T ds, T f) {
+  constexpr int kOther = CX == 0 ? kDppShr1 : kDppShl1;
+  const T q = fma_t(T(0.25), dn + ds, e);
+  return fma_t(T(0.2), (q + lane_shift<kOther>(q)) + (sn + ss), f);
+}
+
+// The rows r_lo..r_hi (all K rows when CHECKED is false) of colour C in a
+// thread's strip; xs / xd: the N / S and diagonal neighbour values of the row
+// beyond the strip (from LDS), used by the row visited last.
+template <typename T, int K, int C, bool CHECKED>
+__device__ __forceinline__ void strip_rows(T (&pv)[4][K], const T (&fv)[4][K], T xs, T xd, T wl,
+                                           int r_lo, int r_hi) {
+  constexpr int cx = C & 1, cy = C >> 1;
+  constexpr int EW = cy * 2 + (1 - cx), NS = (1 - cy) * 2 + cx, DG = (1 - cy) * 2 + (1 - cx);
+  if (cy == 0) {
+    // rows K-1 down to 0; row r's N-side neighbours are in row r of the
+    // y-parity-1 planes, its S-side ones in row r - 1 (LDS for r = 0)
+    T sN = pv[NS][K - 1], dN = pv[DG][K - 1];
+#pragma unroll
+    for (int r = K - 1; r >= 0; --r) {
+      const T sS = r > 0 ? pv[NS][r - 1] : xs;
+      const T dS = r > 0 ? pv[DG][r - 1] : xd;
+      if (!CHECKED || (r >= r_lo && r <= r_hi)) {  // wave-uniform
+        const T p = pv[C][r];
+        pv[C][r] = fma_t(wl, gs_target<cx>(pv[EW][r], sN, sS, dN, dS, fv[C][r]) - p, p);
+      }
+      sN = sS;
+      dN = dS;
+    }
+  } else {
+    // rows 0 up to K-1; row r's S-side neighbours are in row r of the
+    // y-parity-0 planes, its N-side ones in row r + 1 (LDS for r = K - 1)
+    T sS = pv[NS][0], dS = pv[DG][0];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const T sN = r + 1 < K ? pv[NS][r + 1] : xs;
+      const T dN = r + 1 < K ? pv[DG][r + 1] : xd;
+      if (!CHECKED || (r >= r_lo && r <= r_hi)) {  // wave-uniform
+        const T p = pv[C][r];
+        pv[C][r] = fma_t(wl, gs_target<cx>(pv[EW][r], sN, sS, dN, dS, fv[C][r]) - p, p);
+      }
+      sS = sN;
+      dS = dN;
+    }
+  }
+}
+
 // One colour pass C (parity class (C & 1, C >> 1)) of pass number k over the
 // nodes this thread owns.  sp points at the first plane.
 //
@@ -195,14 +255,20 @@ template <> struct Pair<float> { using type = float2; };
 //     row beyond the strip's end;
 //   * diagonals: as N / S in the fourth colour, with the lane shift.
 // Only that row beyond the strip (below its first row for cy = 0, above its
-// last for cy = 1) crosses to another wavefront: it is read from LDS, where
-// its owner publishes it.  After updating colour C a strip therefore
-// publishes one row: its first for cy = 0 (read by the strip below in the
-// cy = 1 passes), its last for cy = 1 (read by the strip above in the next
-// sweep's cy = 0 passes).  Passes 0 and 1 read only what passes 2 and 3 of
-// the previous sweep published, passes 2 and 3 only what passes 0 and 1
-// published, so a barrier after passes 1 and 3 orders every exchange and
-// also keeps each published row from being overwritten while still read.
+// last for cy = 1) crosses to another wavefront: its owner publishes it in
+// LDS, and the caller reads it once per pair of passes (xs: the N / S
+// neighbour plane's value, xd: the diagonal plane's).  After updating colour
+// C a strip therefore publishes one row: its first for cy = 0 (read by the
+// strip below in the cy = 1 passes), its last for cy = 1 (read by the strip
+// above in the next sweep's cy = 0 passes).  Passes 0 and 1 read only what
+// passes 2 and 3 of the previous sweep published, passes 2 and 3 only what
+// passes 0 and 1 published, so a barrier after passes 1 and 3 orders every
+// exchange and also keeps each published row from being overwritten while
+// still read.
+//
+// The row that needs the value from LDS is visited last: top-down for
+// cy = 0, bottom-up for cy = 1, so the LDS read's latency hides behind the
+// other rows' updates.
 //
 // Lanes outside the pass relax with 0 (they keep their value) so the pass
 // has no divergent branch; rows outside it are skipped (wave-uniform).  Only
@@ -212,7 +278,7 @@ template <typename T, int TX, int TY, int S, int NT, int HX, int C>
 __device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
                                             const T (&fv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
                                             int k, int lxd0, int lxd1, int lyd0, int lyd1,
-                                            int lane, int b0, T w) {
+                                            int lane, int b0, T w, T xs, T xd) {
   using G = SorGeom<T, TX, TY, S, NT, HX>;
   constexpr int K = G::K;
   constexpr int cx = C & 1, cy = C >> 1;
@@ -223,43 +289,13 @@ __device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][SorGeom<T, TX, TY,
   // the strip's rows inside the pass (wave-uniform)
   const int r_lo = max((lylo - cy + 1) >> 1, b0) - b0;
   const int r_hi = min((lyhi - cy) >> 1, b0 + K - 1) - b0;
-  const int ic = min(lane, G::RXH - 1);
-  constexpr int kOther = cx == 0 ? kDppShr1 : kDppShl1;
   const T wl = (lane >= a0 && lane <= a1) ? w : T(0);
-  const T c4 = T(0.2), cd = T(0.05);
   if (r_lo <= r_hi) {
-    // S-side values of the first row and the N-side values beyond the last:
-    // the row outside the strip comes from LDS (the padding rows keep it
-    // inside LDS; its values are only used for rows inside the pass)
-    T sS, dS, bN = T(0), bdN = T(0);
-    if (cy == 0) {
-      sS = sp[NS * G::PLANE + (b0 - 1) * G::RXH + ic];
-      dS = sp[DG * G::PLANE + (b0 - 1) * G::RXH + ic];
-    } else {
-      sS = pv[NS][0];
-      dS = pv[DG][0];
-      bN = sp[NS * G::PLANE + (b0 + K) * G::RXH + ic];
-      bdN = sp[DG * G::PLANE + (b0 + K) * G::RXH + ic];
-    }
-    T dSo = lane_shift<kOther>(dS);
-#pragma unroll
-    for (int r = 0; r < K; ++r) {
-      const T sN = cy == 0 ? pv[NS][r] : (r + 1 < K ? pv[NS][r + 1] : bN);
-      const T dN = cy == 0 ? pv[DG][r] : (r + 1 < K ? pv[DG][r + 1] : bdN);
-      const T dNo = lane_shift<kOther>(dN);
-      if (r >= r_lo && r <= r_hi) {  // wave-uniform
-        const T e = pv[EW][r];
-        const T eo = lane_shift<kOther>(e);
-        const T s4 = (e + eo) + (sN + sS);
-        const T sd = (dN + dNo) + (dS + dSo);
-        const T p = pv[C][r];
-        const T g = fma_t(c4, s4, fma_t(cd, sd, fv[C][r]));
-        pv[C][r] = fma_t(wl, g - p, p);
-      }
-      sS = sN;
-      dS = dN;
-      dSo = dNo;
-    }
+    // most strips lie inside the pass entirely: their rows need no test
+    if (r_lo == 0 && r_hi == K - 1)
+      strip_rows<T, K, C, false>(pv, fv, xs, xd, wl, 0, K - 1);
+    else
+      strip_rows<T, K, C, true>(pv, fv, xs, xd, wl, r_lo, r_hi);
     // publish the strip's boundary row of colour C (lanes beyond a plane row
     // store to the sink)
     constexpr int rp = cy == 0 ? 0 : K - 1;
@@ -293,9 +329,7 @@ __device__ __forceinline__ void residual_pass(const T* pl,
   const int r_hi = min((lyhi - cy) >> 1, b0 + K - 1) - b0;
   if (r_lo > r_hi) return;
   const int ic = min(lane, G::RXH - 1);
-  constexpr int kOther = cx == 0 ? kDppShr1 : kDppShl1;
   const bool lane_in = lane >= a0 && lane <= a1;
-  const T c4 = T(0.2), cd = T(0.05);
   T sS, dS, bN = T(0), bdN = T(0);
   if (cy == 0) {
     sS = pl[NS * G::PLANE + (b0 - 1) * G::RXH + ic];
@@ -306,19 +340,13 @@ __device__ __forceinline__ void residual_pass(const T* pl,
     bN = pl[NS * G::PLANE + (b0 + K) * G::RXH + ic];
     bdN = pl[DG * G::PLANE + (b0 + K) * G::RXH + ic];
   }
-  T dSo = lane_shift<kOther>(dS);
 #pragma unroll
   for (int r = 0; r < K; ++r) {
     const T sN = cy == 0 ? pv[NS][r] : (r + 1 < K ? pv[NS][r + 1] : bN);
     const T dN = cy == 0 ? pv[DG][r] : (r + 1 < K ? pv[DG][r + 1] : bdN);
-    const T dNo = lane_shift<kOther>(dN);
     if (r >= r_lo && r <= r_hi) {  // wave-uniform
-      const T e = pv[EW][r];
-      const T eo = lane_shift<kOther>(e);
-      const T s4 = (e + eo) + (sN + sS);
-      const T sd = (dN + dNo) + (dS + dSo);
       const T p = pv[C][r];
-      const T g = fma_t(c4, s4, fma_t(cd, sd, fv[C][r]));
+      const T g = gs_target<cx>(pv[EW][r], sN, sS, dN, dS, fv[C][r]);
       if (lane_in) {
         rmax = fmax(rmax, mag((double)(g - p)));
         pmax = fmax(pmax, mag((double)p));
@@ -326,7 +354,6 @@ __device__ __forceinline__ void residual_pass(const T* pl,
     }
     sS = sN;
     dS = dN;
-    dSo = dNo;
   }
 }
 
@@ -345,6 +372,9 @@ __device__ inline void coh_store(T* p, T v) {
 // Wait until this wavefront's global loads and stores have completed (and its
 // device-scope stores are visible device-wide): s_waitcnt vmcnt(0).
 __device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// s_waitcnt lgkmcnt(0) (vmcnt and expcnt left at their maxima): every LDS
+// and scalar memory read of this wavefront has returned.
+constexpr int kWaitLgkm0 = 0xC07F;
 
 // Phases of a tile, shared by the per-launch, batched and resident kernels.
 // Region coordinates: x0, y0 is the global position of local (0, 0), even.
@@ -474,19 +504,35 @@ __device__ __forceinline__ void lds_to_regs(const T* pl, int lane, int b0,
   }
 }
 
-// S sweeps = 4S colour passes over the region.
+// S sweeps = 4S colour passes over the region.  The rows beyond the strip
+// are read from LDS once per pair of passes, right after the barrier that
+// makes them current: below the strip, the y-parity-1 planes (2 and 3) for
+// passes 0 and 1; above it, the y-parity-0 planes (0 and 1) for passes 2 and
+// 3.  Neither pass of a pair writes the planes the pair reads.  (The padding
+// rows keep both reads inside LDS; their values are used only for rows
+// inside a pass.)
 template <typename T, int TX, int TY, int S, int NT, int HX>
 __device__ __forceinline__ void tile_sweeps(T* pl, T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
                                             const T (&fv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
                                             int lxd0, int lxd1, int lyd0, int lyd1, int lane,
                                             int b0, T w) {
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
+  const int ic = min(lane, G::RXH - 1);
+  const T* below = pl + (b0 - 1) * G::RXH + ic;
+  const T* above = pl + (b0 + G::K) * G::RXH + ic;
 #pragma unroll 1
   for (int s = 0; s < S; ++s) {
     const int k = 4 * s;
-    colour_pass<T, TX, TY, S, NT, HX, 0>(pl, pv, fv, k + 1, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
-    colour_pass<T, TX, TY, S, NT, HX, 1>(pl, pv, fv, k + 2, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
-    colour_pass<T, TX, TY, S, NT, HX, 2>(pl, pv, fv, k + 3, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
-    colour_pass<T, TX, TY, S, NT, HX, 3>(pl, pv, fv, k + 4, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
+    const T l2 = below[2 * G::PLANE], l3 = below[3 * G::PLANE];
+    colour_pass<T, TX, TY, S, NT, HX, 0>(pl, pv, fv, k + 1, lxd0, lxd1, lyd0, lyd1, lane, b0, w,
+                                         l2, l3);
+    colour_pass<T, TX, TY, S, NT, HX, 1>(pl, pv, fv, k + 2, lxd0, lxd1, lyd0, lyd1, lane, b0, w,
+                                         l3, l2);
+    const T u0 = above[0], u1 = above[G::PLANE];
+    colour_pass<T, TX, TY, S, NT, HX, 2>(pl, pv, fv, k + 3, lxd0, lxd1, lyd0, lyd1, lane, b0, w,
+                                         u0, u1);
+    colour_pass<T, TX, TY, S, NT, HX, 3>(pl, pv, fv, k + 4, lxd0, lxd1, lyd0, lyd1, lane, b0, w,
+                                         u1, u0);
   }
 }
 
@@ -584,6 +630,11 @@ __device__ __forceinline__ bool sor_tile(const T* __restrict__ pin, T* __restric
   lds_to_regs<T, TX, TY, S, NT, HX, false>(pl, lane, b0, pv);
   const int lxd0 = 1 - x0, lxd1 = n - 2 - x0;  // domain interior in local coordinates
   const int lyd0 = 1 - y0, lyd1 = n - 2 - y0;
+  // Every LDS and scalar read issued so far has arrived before the passes
+  // start: otherwise the waits the compiler places inside the pass loop
+  // cover them on every iteration, and each pass would wait for its own
+  // boundary-row reads at its start instead of at the row that uses them.
+  __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
   tile_sweeps<T, TX, TY, S, NT, HX>(pl, pv, fv, lxd0, lxd1, lyd0, lyd1, lane, b0, w);
   tile_to_global<T, TX, TY, S, NT, HX, COH>(pout, n, pitch, x0, y0, lane, b0, pv);
   double rmax = 0.0, pmax = 0.0;
@@ -1712,14 +1763,17 @@ int sor_max_blocks(int n) { return ((n + 31) / 32) * ((n + 31) / 32); }
   X(64, 64, 3, 512)              \
   X(64, 32, 3, 512)              \
   X(64, 32, 4, 512)              \
-  X(64, 64, 3, 768)
+  X(64, 64, 3, 768)              \
+  X(64, 64, 4, 512)              \
+  X(84, 54, 5, 1024)
 
 #define CAV_BATCH_CONFIGS_F32(X) \
   X(32, 32, 1, 256)              \
   X(64, 32, 2, 512)              \
   X(64, 64, 2, 1024)             \
   X(64, 64, 4, 1024)             \
-  X(96, 64, 3, 1024)
+  X(96, 64, 3, 1024)             \
+  X(88, 56, 5, 1024)
 
 bool batch_config_supported(const SorConfig& c, bool mixed) {
   if (c.xcd_bands != 0) return false;

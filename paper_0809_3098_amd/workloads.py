@@ -22,6 +22,15 @@ WORKLOADS = {
     # where the paper found no solution on that grid; dt as in Table tab:grid
     "grid_dependence": dict(members=[(5000.0, 220), (10000.0, 220), (15000.0, 300),
                                      (20000.0, 300)], dt=1e-3, tol=1e-10, init="rest"),
+    # the fine-grid side of the same study: 1024^2 at the two Reynolds numbers the
+    # paper finds unsteady on 300^2 (Sec. 4)
+    "grid_dependence_1024": dict(members=[(15000.0, 1024), (20000.0, 1024)], dt=1e-3, tol=1e-10,
+                                 init="rest"),
+    # Table tab:grid of Sec. 4: the production runs at 1024^2 with dt = 0.001, run until
+    # the Sec. 4 thresholds on RES_psi and RES_omega hold
+    "steady_table_1024": dict(members=[(5000.0, 1024), (10000.0, 1024), (15000.0, 1024),
+                                       (20000.0, 1024), (25000.0, 1024), (30000.0, 1024)],
+                              dt=1e-3, tol=1e-10, init="rest"),
     "cavity4096_re3e4_mixed_noise": dict(n=4096, re=3.0e4, steps=2000, tol=1e-10,
                                          precision="mixed", init="noise",
                                          noise_amplitude=1e-3, noise_seed=0),

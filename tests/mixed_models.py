@@ -29,14 +29,23 @@ import numpy as np
 
 from oracle.cavity_oracle import CavityOracle, transport_rhs
 
-#: Tolerance = FACTOR x the error of the precision design's model.  The GPU
-#: rounds differently (fused multiply-adds, its own operation order), so its
-#: error is a different draw of the same rounding noise; 3 covers that while
-#: staying below the defective run's error on the workloads the tests use.
-FACTOR = 3.0
-#: FP64-level floor added to every tolerance (the design's error is never
-#: below what the FP64 path itself may differ by).
+#: Tolerance = FACTOR x the error of the precision design's model for psi and
+#: omega.  The GPU rounds differently (fused multiply-adds, its own operation
+#: order), so its error is a different draw of the same rounding noise
+#: (measured: up to 2.2 times the model's); 4 covers that while staying below
+#: the defective run's error on the workloads the tests use.
+FACTOR = 4.0
+#: The kinetic energy is a sum over the whole field, so a different draw of
+#: the rounding shifts it more (measured: 3.5 times the model's); storing
+#: omega in FP32 does not change it much, so its tolerance is not what
+#: rejects the defective run and may be looser.
+FACTOR_KE = 8.0
+#: FP64-level floor added to every tolerance: the FP64 path's own parity bound.
 FLOOR = 1e-11
+#: ||A^-1||_inf of the compact operator on the unit square (the torsion
+#: maximum; 0.07367 from 65^2 to 1025^2): a converged solve's error in psi is
+#: at most this times its residual max-norm.
+INV_NORM = 0.0737
 
 
 class MixedModel(CavityOracle):
@@ -113,15 +122,26 @@ def _cached(n, re, steps, init_key, dt, interior):
     return ref, _errors(model, ref), _errors(bad, ref)
 
 
-def mixed_tolerances(n, re, steps, init_key=None, dt=None, interior=0):
+def mixed_tolerances(n, re, steps, init_key=None, dt=None, interior=0, poisson_tol=1e-10):
     """(reference fields, tolerances, design errors, defective-run errors).
 
     reference = (psi, omega, ke) of the FP64 oracle (cropped to nodes at least
     ``interior`` from every wall when ``interior`` > 0).  Tolerances are
-    FACTOR x the design's errors plus FLOOR, per quantity.
+    FACTOR (FACTOR_KE) x the design's errors plus FLOOR, per quantity, plus
+    what the iterative solve may leave: the model solves exactly, the GPU
+    refines psi until the residual max-norm is below ``poisson_tol``, so psi
+    may differ by up to INV_NORM * poisson_tol (twice that, for the solves
+    before the last), omega's walls by 2 / h^2 times that (Thom's formula) and
+    the kinetic energy by twice psi's relative error.
     """
     ref, model, bad = _cached(n, re, steps, init_key, dt, interior)
-    tol = {k: FACTOR * v + FLOOR for k, v in model.items()}
+    h = 1.0 / (n - 1)
+    dpsi = 2.0 * INV_NORM * poisson_tol
+    solve = {"psi": dpsi / np.max(np.abs(ref[0])),
+             "omega": 2.0 / (h * h) * dpsi / np.max(np.abs(ref[1]))}
+    solve["ke"] = 2.0 * solve["psi"]
+    tol = {k: (FACTOR_KE if k == "ke" else FACTOR) * v + solve[k] + FLOOR
+           for k, v in model.items()}
     return ref, tol, model, bad
 
 

@@ -6,7 +6,7 @@
   leave an error of ||A^-1|| * tol in psi, so the comparison uses that bound
   (||A^-1||_inf computed by the oracle, the residual reported by the GPU);
   omega inherits the psi error through Thom's wall formula (2 / h^2), and the
-  mixed path adds 3 times the error of the precision design's CPU model
+  mixed path adds 4 times the error of the precision design's CPU model
   (``mixed_models.MixedModel``: eq. (Lwn) in FP32) for psi and omega.  Here
   the solver-tolerance term through Thom's 2 / h^2 (about 1e-3) exceeds what
   storing omega in FP32 would cost (about 4e-4), so this one-step check
