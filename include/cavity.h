@@ -203,6 +203,35 @@ int cavity_poisson(cavity_t h, int32_t idx, const double* d_omega, double* d_psi
                    cavity_poisson_info* info);
 
 /*
+ * Allocation-free Poisson solve, for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid allocation): the same
+ * FP64 four-colour SOR solve of the compact stream equation as cavity_poisson
+ * with a vorticity given (from a zero start, with the relaxation, sweep kernel
+ * and residual-check spacing a cavity of this n gets by default, so the result
+ * is bitwise that of cavity_poisson on such a cavity), without a handle.  Its
+ * right-hand side, iterate pair, partial maxima and control block live in a
+ * device array of the library, 24 MiB + 64 KiB per device, held from the
+ * first call on a device until the process ends; the call allocates no memory
+ * (no hipMalloc, hipFree or host pinning).  Every call on one device uses
+ * that device's array: calls that overlap on one device (other host threads,
+ * other streams) race and must not be made.
+ *   n              5 <= n <= 1024 (nodes per side including walls); larger n
+ *                  -> CAVITY_EINVAL
+ *   poisson_tol    as in cavity_params (<= 0 means 1e-10)
+ *   sor_omega      as in cavity_params (<= 0: the default relaxation)
+ *   poisson_max_sweeps  as in cavity_params (0 means 200 * n)
+ *   d_omega        device n*n vorticity (walls included), read only
+ *   d_psi          device n*n output for psi (walls 0)
+ *   hip_stream     stream of the current device the work is enqueued on
+ *   info           nullable host result
+ * Synchronises the stream (the host reads the stopping decision).  Errors:
+ * EINVAL, EHIP, ENOCONV (psi holds the last iterate), ENONFINITE.
+ */
+int cavity_poisson_noalloc(int32_t n, double poisson_tol, double sor_omega,
+                           int32_t poisson_max_sweeps, const double* d_omega, double* d_psi,
+                           void* hip_stream, cavity_poisson_info* info);
+
+/*
  * Copy out the fields of cavity idx as device n*n double arrays; each pointer
  * is nullable.  u, v follow eq. (vel) inside and the wall values of Sec. 3.1
  * (u = U on the lid row except its corners, 0 elsewhere; v = 0 on walls).

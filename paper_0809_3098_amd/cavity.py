@@ -111,6 +111,9 @@ _lib.cavity_run_steady.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
                                    _P(cavity_stats)]
 _lib.cavity_poisson.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                 ctypes.c_void_p, _P(cavity_poisson_info)]
+_lib.cavity_poisson_noalloc.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, _P(cavity_poisson_info)]
 _lib.cavity_fields.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p]
 _lib.cavity_relax.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -124,13 +127,13 @@ _lib.cavity_get_exec.argtypes = [ctypes.c_void_p, _P(ctypes.c_int32)]
 _lib.cavity_destroy.argtypes = [ctypes.c_void_p]
 _lib.cavity_last_error.restype = ctypes.c_char_p
 for _f in ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_run_steady",
-           "cavity_poisson",
+           "cavity_poisson", "cavity_poisson_noalloc",
            "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
            "cavity_set_exec", "cavity_get_exec", "cavity_autotune", "cavity_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_run_steady",
-            "cavity_poisson",
+            "cavity_poisson", "cavity_poisson_noalloc",
             "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
             "cavity_set_exec", "cavity_get_exec", "cavity_autotune", "cavity_destroy",
             "cavity_last_error")
@@ -228,6 +231,19 @@ def cavity_poisson(h: int, idx: int, omega_ptr: int = 0, psi_ptr: int = 0,
                              ctypes.byref(info) if want_info else None)
     _check(rc, allow=(CAVITY_ENOCONV,) if allow_noconv else ())
     return info.as_dict() if want_info else None
+
+
+def cavity_poisson_noalloc(n: int, omega_ptr: int, psi_ptr: int, stream_ptr: int,
+                           poisson_tol: float = 0.0, sor_omega: float = 0.0,
+                           poisson_max_sweeps: int = 0, allow_noconv: bool = False) -> dict:
+    """Handle-free Poisson solve whose scratch is the library's device array."""
+    info = cavity_poisson_info()
+    rc = _lib.cavity_poisson_noalloc(n, poisson_tol, sor_omega, poisson_max_sweeps,
+                                     ctypes.c_void_p(omega_ptr or None),
+                                     ctypes.c_void_p(psi_ptr or None),
+                                     ctypes.c_void_p(stream_ptr or None), ctypes.byref(info))
+    _check(rc, allow=(CAVITY_ENOCONV,) if allow_noconv else ())
+    return info.as_dict()
 
 
 def cavity_fields(h: int, idx: int, psi_ptr: int = 0, omega_ptr: int = 0, u_ptr: int = 0,

@@ -237,4 +237,11 @@ hipError_t launch_copy(const double* src, double* dst, int n, int pitch, hipStre
 hipError_t launch_copy_interior(const double* src, double* dst, int n, int pitch,
                                 hipStream_t st);
 
+// Allocation-free Poisson solve: the largest grid it takes, the size of its
+// device scratch array, and that array's address on the current device
+// (looked up with hipGetSymbolAddress on the first call per device).
+int noalloc_max_n();
+size_t noalloc_bytes();
+hipError_t noalloc_scratch(void** out);
+
 }  // namespace cav

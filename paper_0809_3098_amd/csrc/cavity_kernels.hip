@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "cavity_internal.h"
@@ -1984,6 +1985,46 @@ hipError_t launch_copy_interior(const double* src, double* dst, int n, int pitch
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Scratch memory of the allocation-free Poisson solve (cavity_poisson_noalloc):
+// a file-scope device array that each device holds for the life of the
+// process.  Host code never passes the array's name to a kernel (in host code
+// it is a host-side stand-in, not a device address): noalloc_scratch returns
+// the address hipGetSymbolAddress gives for the current device, looked up
+// once per device.
+// ---------------------------------------------------------------------------
+constexpr int kNoAllocMaxN = 1024;
+// three pitched FP64 fields of the largest grid (right-hand side and the
+// iterate's ping-pong pair; pitch(1024) = 1024), then 64 KiB for the partial
+// maxima of the residual checks and the control block
+constexpr size_t kNoAllocFieldBytes = (size_t)kNoAllocMaxN * kNoAllocMaxN * sizeof(double);
+constexpr size_t kNoAllocBytes = 3 * kNoAllocFieldBytes + 64 * 1024;
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+int noalloc_max_n() { return kNoAllocMaxN; }
+size_t noalloc_bytes() { return kNoAllocBytes; }
+
+hipError_t noalloc_scratch(void** out) {
+  static std::mutex mu;
+  static void* ptr[kNoAllocMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return hipSuccess;
+}
 
 // Tile shapes of the resident solve.
 #define CAV_RESIDENT_CONFIGS(X) \

@@ -1640,6 +1640,95 @@ int cavity_poisson(cavity_t h, int32_t idx, const double* d_omega, double* d_psi
   return rc;
 }
 
+int cavity_poisson_noalloc(int32_t n, double poisson_tol, double sor_omega,
+                           int32_t poisson_max_sweeps, const double* d_omega, double* d_psi,
+                           void* hip_stream, cavity_poisson_info* info) {
+  if (!d_omega || !d_psi) return fail(CAVITY_EINVAL, "d_omega and d_psi are required");
+  if (n < 5 || n > cav::noalloc_max_n())
+    return fail(CAVITY_EINVAL, "n = %d outside [5, %d], the grids the allocation-free solve's "
+                               "scratch array holds", n, cav::noalloc_max_n());
+  if (poisson_max_sweeps < 0) return fail(CAVITY_EINVAL, "poisson_max_sweeps must be >= 0");
+  // the same derived solve parameters as a cavity of this size with default
+  // tuning (relaxation, sweep kernel, check spacing, stall window, limits)
+  cavity_params p{};
+  p.n = n;
+  p.re = 1.0;
+  p.u_lid = 1.0;
+  p.poisson_tol = poisson_tol;
+  p.poisson_max_sweeps = poisson_max_sweeps;
+  p.sor_omega = sor_omega;
+  Member m;
+  int rc = derive(p, m);
+  if (rc != CAVITY_OK) return rc;
+  cavity_s* const none = nullptr;  // no handle to poison
+  void* base = nullptr;
+  HIP_TRY(none, cav::noalloc_scratch(&base));
+  // carve the scratch array: F, the iterate's pair, partial maxima, control
+  const size_t f64 = align_up((size_t)m.n * m.pitch * sizeof(double));
+  const size_t partb = align_up(part_doubles(m.n) * sizeof(double));
+  if (3 * f64 + partb + align_up(sizeof(cav::PoissonCtl)) > cav::noalloc_bytes())
+    return fail(CAVITY_EINVAL, "n = %d does not fit the scratch array", n);
+  char* cur = static_cast<char*>(base);
+  m.F = reinterpret_cast<double*>(cur);
+  m.psi = reinterpret_cast<double*>(cur + f64);
+  m.psi_b = reinterpret_cast<double*>(cur + 2 * f64);
+  m.part = reinterpret_cast<double*>(cur + 3 * f64);
+  m.ctl = reinterpret_cast<cav::PoissonCtl*>(cur + 3 * f64 + partb);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // omega (pitched, in psi_b for the moment) -> F; both iterates start at 0
+  // (walls included), whatever an earlier call left in the array
+  HIP_TRY(none, cav::launch_copy_in(d_omega, m.psi_b, m.n, m.pitch, st));
+  HIP_TRY(none, cav::launch_poisson_rhs(m.psi_b, m.F, m.n, m.pitch, m.h, st));
+  HIP_TRY(none, cav::launch_fill(m.psi, m.n, m.pitch, 0.0, st));
+  HIP_TRY(none, cav::launch_fill(m.psi_b, m.n, m.pitch, 0.0, st));
+  const double tol_hat = m.tol * 0.3 * m.h * m.h;
+  const long long spc = unit_sweeps(m);
+  HIP_TRY(none, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, m.stall_window, spc,
+                                      st));
+  HIP_TRY(none, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, m.part,
+                                    st));
+  // chunks of check groups until the device's decision stops the solve; the
+  // decision is read into host stack memory
+  cav::PoissonCtl c{};
+  long long enqueued = 0;
+  for (;;) {
+    long long units = enqueued == 0 ? std::max<long long>(4, (long long)(0.5 * (m.n - 1) / spc))
+                                    : std::max<long long>(2, enqueued / 4);
+    units = std::max<long long>(1, std::min<long long>(units, m.max_sweeps / spc + 1));
+    for (long long u = 0; u < units; ++u) {
+      for (int q = 0; q < m.pairs_per_check; ++q) {
+        const int check = (q == m.pairs_per_check - 1) ? 1 : 0;
+        HIP_TRY(none, cav::launch_sor64(m.cfg64, m.psi, m.psi_b, m.F, m.n, m.pitch, m.ctl,
+                                        m.part, 0, st));
+        HIP_TRY(none, cav::launch_sor64(m.cfg64, m.psi_b, m.psi, m.F, m.n, m.pitch, m.ctl,
+                                        m.part, check, st));
+      }
+    }
+    enqueued += units;
+    HIP_TRY(none, hipMemcpyAsync(&c, m.ctl, sizeof c, hipMemcpyDeviceToHost, st));
+    HIP_TRY(none, hipStreamSynchronize(st));
+    if (c.state != cav::SOLVE_RUN) break;
+    if (enqueued * spc > 2 * m.max_sweeps + 64 * spc)
+      return fail(CAVITY_EHIP, "allocation-free Poisson solve made no decision after %lld "
+                               "sweeps", enqueued * spc);
+  }
+  HIP_TRY(none, cav::launch_copy_out(m.psi, d_psi, m.n, m.pitch, st));
+  HIP_TRY(none, hipStreamSynchronize(st));
+  const double resid = c.last * (10.0 / 3.0) / (m.h * m.h);
+  if (info) {
+    info->sweeps = c.sweeps;
+    info->resid_inf = resid;
+    info->floor_limited = c.state == cav::SOLVE_FLOOR ? 1 : 0;
+    info->status = c.state == cav::SOLVE_NOCONV ? CAVITY_ENOCONV : CAVITY_OK;
+  }
+  if (c.state == cav::SOLVE_NONFINITE)
+    return fail(CAVITY_ENONFINITE, "non-finite residual in the allocation-free Poisson solve");
+  if (c.state == cav::SOLVE_NOCONV)
+    return fail(CAVITY_ENOCONV, "allocation-free Poisson solve hit %lld sweeps (residual %g)",
+                (long long)c.sweeps, resid);
+  return CAVITY_OK;
+}
+
 int cavity_fields(cavity_t h, int32_t idx, double* d_psi, double* d_omega, double* d_u,
                   double* d_v) {
   if (!h) return fail(CAVITY_EINVAL, "null handle");

@@ -124,3 +124,11 @@ def test_create_rejects_before_touching_a_device(binding):
     with pytest.raises(binding.CavityError) as e:
         binding.cavity_step(0, 1)
     assert e.value.code == binding.CAVITY_EINVAL
+
+
+def test_noalloc_solve_rejects_before_touching_a_device(binding):
+    """The allocation-free solve checks its arguments before any HIP call."""
+    for n, ptr in ((1025, 256), (4, 256), (64, 0)):
+        with pytest.raises(binding.CavityError) as e:
+            binding.cavity_poisson_noalloc(n, ptr, ptr, 0)
+        assert e.value.code == binding.CAVITY_EINVAL
