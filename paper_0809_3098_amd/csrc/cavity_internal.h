@@ -37,6 +37,8 @@ struct alignas(128) PoissonCtl {
   long long max_sweeps;
   long long stall_window;     // sweeps without halving that mean stagnation
   long long sweeps_per_check; // sweeps between two checks
+  double floor_ulps;          // > 0: a residual within this many ulps of max |psi| is the
+                              // rounding floor and stops the solve (floor-limited)
   int floor_limited;
   int werror;                 // 1: a wait of a resident solve timed out
   // Totals over every solve since the handle was created (never reset by a
@@ -134,7 +136,7 @@ hipError_t launch_stage(const double* psi, const float* psi32, const double* w0,
 // Reset a solve's control block (a kernel, so it can live in a graph).
 hipError_t launch_ctl_reset(PoissonCtl* ctl, double relax, double tol_hat,
                             long long max_sweeps, long long stall_window,
-                            long long sweeps_per_check, hipStream_t st);
+                            long long sweeps_per_check, hipStream_t st, double floor_ulps = 0.0);
 
 // One launch of `cfg.s` four-colour sweeps, psi_in -> psi_out (ping-pong).
 // check != 0: also the residual of the result and the solve decision.
@@ -201,6 +203,19 @@ hipError_t launch_mg_prolong(const double* Ec, int nc, int pitchc, double* psi, 
                              int pitchf, const PoissonCtl* ctl, hipStream_t st);
 hipError_t launch_mg_prolong(const float* Ec, int nc, int pitchc, float* psi, int nf,
                              int pitchf, const PoissonCtl* ctl, hipStream_t st);
+// The coarse end of a V-cycle in one block: levels n[0] > n[1] > ... (the
+// first with at most mg_fuse_max() nodes a side, down to the coarsest), nu
+// smoothing sweeps (relaxation 1) before and after each coarse correction,
+// coarse_sweeps sweeps with coarse_relax on the coarsest level; E (in and out,
+// interior written) and F are level n[0]'s pitched arrays.  Same arithmetic,
+// so the same bits, as the per-level launches.
+int mg_fuse_max();
+hipError_t launch_mg_fused(double* E, const double* F, int pitch, const int* n, int levels,
+                           int nu, int coarse_sweeps, double coarse_relax, const PoissonCtl* ctl,
+                           hipStream_t st);
+hipError_t launch_mg_fused(float* E, const float* F, int pitch, const int* n, int levels, int nu,
+                           int coarse_sweeps, double coarse_relax, const PoissonCtl* ctl,
+                           hipStream_t st);
 hipError_t launch_sor64_relax(const SorConfig& cfg, const double* psi_in, double* psi_out,
                               const double* F, int n, int pitch, PoissonCtl* ctl, double relax,
                               hipStream_t st);

@@ -72,6 +72,11 @@ __device__ void decide(PoissonCtl* c, double r, double pm, long long sweeps_done
     st = SOLVE_NONFINITE;
   } else if (r <= c->tol_hat) {
     st = SOLVE_CONVERGED;
+  } else if (c->floor_ulps > 0.0 && r <= c->floor_ulps * DBL_EPSILON * pm) {
+    // The residual is at the rounding level of psi itself: no iteration can
+    // lower it further (multigrid reaches it in a few cycles).
+    st = SOLVE_FLOOR;
+    c->floor_limited = 1;
   } else {
     if (r < 0.5 * c->best) {
       c->best = r;
@@ -202,10 +207,12 @@ __device__ __forceinline__ T gs_target(T e, T sn, T ss, T dn, T ds, T f) {
   return fma_t(T(0.2), (q + lane_shift<kOther>(q)) + (sn + ss), f);
 }
 
-// The rows r_lo..r_hi (all K rows when CHECKED is false) of colour C in a
-// thread's strip; xs / xd: the N / S and diagonal neighbour values of the row
-// beyond the strip (from LDS), used by the row visited last.
-template <typename T, int K, int C, bool CHECKED>
+// The rows r_lo..r_hi of colour C in a thread's strip; xs / xd: the N / S
+// and diagonal neighbour values of the row beyond the strip (from LDS), used
+// by the row visited last.  (A second copy of the loop without the row tests,
+// for strips that lie inside the pass, doubled the vector instructions per
+// sweep: the compiler copied the register arrays between the two versions.)
+template <typename T, int K, int C>
 __device__ __forceinline__ void strip_rows(T (&pv)[4][K], const T (&fv)[4][K], T xs, T xd, T wl,
                                            int r_lo, int r_hi) {
   constexpr int cx = C & 1, cy = C >> 1;
@@ -218,7 +225,7 @@ __device__ __forceinline__ void strip_rows(T (&pv)[4][K], const T (&fv)[4][K], T
     for (int r = K - 1; r >= 0; --r) {
       const T sS = r > 0 ? pv[NS][r - 1] : xs;
       const T dS = r > 0 ? pv[DG][r - 1] : xd;
-      if (!CHECKED || (r >= r_lo && r <= r_hi)) {  // wave-uniform
+      if (r >= r_lo && r <= r_hi) {  // wave-uniform
         const T p = pv[C][r];
         pv[C][r] = fma_t(wl, gs_target<cx>(pv[EW][r], sN, sS, dN, dS, fv[C][r]) - p, p);
       }
@@ -233,7 +240,7 @@ __device__ __forceinline__ void strip_rows(T (&pv)[4][K], const T (&fv)[4][K], T
     for (int r = 0; r < K; ++r) {
       const T sN = r + 1 < K ? pv[NS][r + 1] : xs;
       const T dN = r + 1 < K ? pv[DG][r + 1] : xd;
-      if (!CHECKED || (r >= r_lo && r <= r_hi)) {  // wave-uniform
+      if (r >= r_lo && r <= r_hi) {  // wave-uniform
         const T p = pv[C][r];
         pv[C][r] = fma_t(wl, gs_target<cx>(pv[EW][r], sN, sS, dN, dS, fv[C][r]) - p, p);
       }
@@ -292,11 +299,7 @@ __device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][SorGeom<T, TX, TY,
   const int r_hi = min((lyhi - cy) >> 1, b0 + K - 1) - b0;
   const T wl = (lane >= a0 && lane <= a1) ? w : T(0);
   if (r_lo <= r_hi) {
-    // most strips lie inside the pass entirely: their rows need no test
-    if (r_lo == 0 && r_hi == K - 1)
-      strip_rows<T, K, C, false>(pv, fv, xs, xd, wl, 0, K - 1);
-    else
-      strip_rows<T, K, C, true>(pv, fv, xs, xd, wl, r_lo, r_hi);
+    strip_rows<T, K, C>(pv, fv, xs, xd, wl, r_lo, r_hi);
     // publish the strip's boundary row of colour C (lanes beyond a plane row
     // store to the sink)
     constexpr int rp = cy == 0 ? 0 : K - 1;
@@ -370,6 +373,30 @@ template <typename T>
 __device__ inline void coh_store(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Device-coherent 16-byte accesses of a pair of doubles: buffer loads and
+// stores with the device-scope cache bit (sc1), through a buffer resource
+// over the whole array (records beyond it read 0 and are not written, so a
+// wrong offset cannot fault).  One instruction per pair instead of two
+// 8-byte atomics.
+constexpr int kCacheSc1 = 16;                  // cache-policy bit sc1
+constexpr int kBufferDword3 = 0x00020000;      // raw buffer, 32-bit data format
+__device__ inline __amdgpu_buffer_rsrc_t coh_buffer(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                           (int)min(bytes, (size_t)0x7fffffff), kBufferDword3);
+}
+__device__ inline double2 coh_load_pair(__amdgpu_buffer_rsrc_t r, size_t index) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(
+                                         r, (int)(index * sizeof(double)), 0, kCacheSc1));
+}
+__device__ inline void coh_store_pair(__amdgpu_buffer_rsrc_t r, size_t index, double a, double b) {
+  double2 v;
+  v.x = a;
+  v.y = b;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r,
+                                         (int)(index * sizeof(double)), 0, kCacheSc1);
+}
+
 // Wait until this wavefront's global loads and stores have completed (and its
 // device-scope stores are visible device-wide): s_waitcnt vmcnt(0).
 __device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
@@ -394,6 +421,8 @@ __device__ __forceinline__ void region_to_lds(const T* __restrict__ pin, int n, 
   constexpr int NPAIR = RXP * G::RY;
   constexpr int NL = (NPAIR + NT - 1) / NT;
   constexpr int CH = (CHUNK > 0 && CHUNK < NL) ? CHUNK : NL;
+  static_assert(!COHERENT || std::is_same<T, double>::value, "coherent tiles are FP64");
+  const __amdgpu_buffer_rsrc_t crs = coh_buffer(pin, (size_t)n * pitch * sizeof(T));
 #pragma unroll
   for (int q0 = 0; q0 < NL; q0 += CH) {
     T2 lv[CH];
@@ -411,9 +440,10 @@ __device__ __forceinline__ void region_to_lds(const T* __restrict__ pin, int n, 
         const int gx = x0 + lx, gy = y0 + ly;
         if ((unsigned)gy < (unsigned)n && (unsigned)gx < (unsigned)n) {
           const size_t g = (size_t)gy * pitch + gx;
-          if (COHERENT) {
-            lv[j].x = coh_load(pin + g);
-            if (gx + 1 < n) lv[j].y = coh_load(pin + g + 1);
+          if constexpr (COHERENT) {
+            // the same pair load with the device-scope bit (FP64 only)
+            lv[j] = coh_load_pair(crs, g);
+            zy[j] = gx + 1 >= n;
           } else {
             // One 16-byte load per pair, even for the last pair of an odd
             // grid: gx is even and the pitch even and above n - 1, so gx + 1
@@ -545,6 +575,8 @@ __device__ __forceinline__ void tile_to_global(T* __restrict__ pout, int n, int 
                                                const T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K]) {
   using G = SorGeom<T, TX, TY, S, NT, HX>;
   using T2 = typename Pair<T>::type;
+  static_assert(!COHERENT || std::is_same<T, double>::value, "coherent tiles are FP64");
+  const __amdgpu_buffer_rsrc_t crs = coh_buffer(pout, (size_t)n * pitch * sizeof(T));
 #pragma unroll
   for (int cy = 0; cy < 2; ++cy) {
 #pragma unroll
@@ -559,9 +591,13 @@ __device__ __forceinline__ void tile_to_global(T* __restrict__ pout, int n, int 
       const bool in0 = gx >= 1 && gx <= n - 2;
       const bool in1 = gx + 1 <= n - 2;  // gx + 1 >= 1 always
       const size_t g = (size_t)gy * pitch + gx;
-      if (COHERENT) {
-        if (in0) coh_store(pout + g, pv[2 * cy][r]);
-        if (in1) coh_store(pout + g + 1, pv[2 * cy + 1][r]);
+      if constexpr (COHERENT) {
+        if (in0 && in1) {
+          coh_store_pair(crs, g, pv[2 * cy][r], pv[2 * cy + 1][r]);
+        } else {
+          if (in0) coh_store(pout + g, pv[2 * cy][r]);
+          if (in1) coh_store(pout + g + 1, pv[2 * cy + 1][r]);
+        }
       } else if (in0 && in1) {
         // streaming store: the next launch reads psi from the memory side
         // anyway, and the kernel's end then has fewer lines to write back
@@ -1201,6 +1237,76 @@ __global__ __launch_bounds__(NT) void k_sor_resident(double* __restrict__ bufa,
 // nested levels these are the usual bilinear and full-weighting stencils.
 // Every kernel returns at once when the solve has stopped.
 // ---------------------------------------------------------------------------
+// The per-node arithmetic of the transfer and residual steps, shared by the
+// per-level kernels and the fused coarse cycle so that both give the same
+// bits.  Arrays are row-major with the given pitch (global or LDS).
+
+// r = (g - psi) / (0.3 h^2) at interior node p: the residual of the compact
+// equation in vorticity units.
+template <typename T>
+__device__ __forceinline__ T mg_residual_at(const T* psi, const T* F, size_t p, int pitch,
+                                            T inv03h2) {
+  const T s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pitch] + psi[p - pitch]);
+  const T sd = (psi[p + pitch + 1] + psi[p + pitch - 1]) + (psi[p - pitch + 1] + psi[p - pitch - 1]);
+  const T g = fma_t(T(0.2), s4, fma_t(T(0.05), sd, F[p]));
+  return (g - psi[p]) * inv03h2;
+}
+
+// The restricted residual at interior coarse node (I, J) (before the
+// scaling): the transpose of bilinear interpolation in physical coordinates.
+template <typename T>
+__device__ __forceinline__ T mg_restrict_at(const T* r, int nf, int pitchf, int nc, int I,
+                                            int J) {
+  const long long mf = nf - 1, mc = nc - 1;
+  const int i0 = max(1, (int)(((I - 1) * mf) / mc) + 1);
+  const int i1 = min(nf - 2, (int)(((I + 1) * mf + mc - 1) / mc) - 1);
+  const int j0 = max(1, (int)(((J - 1) * mf) / mc) + 1);
+  const int j1 = min(nf - 2, (int)(((J + 1) * mf + mc - 1) / mc) - 1);
+  const T invmf = T(1) / (T)mf;
+  T sum = T(0);
+  for (int j = j0; j <= j1; ++j) {
+    const long long dj = (long long)j * mc - (long long)J * mf;
+    const T wy = (T)(mf - (dj < 0 ? -dj : dj)) * invmf;
+    if (wy <= T(0)) continue;
+    T row = T(0);
+    for (int i = i0; i <= i1; ++i) {
+      const long long di = (long long)i * mc - (long long)I * mf;
+      const T wx = (T)(mf - (di < 0 ? -di : di)) * invmf;
+      if (wx > T(0)) row = fma_t(wx, r[(size_t)j * pitchf + i], row);
+    }
+    sum = fma_t(wy, row, sum);
+  }
+  return sum;
+}
+
+// The bilinear interpolation of the coarse correction at interior fine node
+// (i, j).
+template <typename T>
+__device__ __forceinline__ T mg_prolong_at(const T* Ec, int nc, int pitchc, int nf, int i, int j) {
+  const long long mf = nf - 1, mc = nc - 1;
+  const int I = (int)(((long long)i * mc) / mf);
+  const int J = (int)(((long long)j * mc) / mf);
+  const T ti = (T)((long long)i * mc - (long long)I * mf) / (T)mf;
+  const T tj = (T)((long long)j * mc - (long long)J * mf) / (T)mf;
+  const size_t c = (size_t)J * pitchc + I;
+  const T lo = fma_t(ti, Ec[c + 1] - Ec[c], Ec[c]);
+  const T hi = fma_t(ti, Ec[c + pitchc + 1] - Ec[c + pitchc], Ec[c + pitchc]);
+  return fma_t(tj, hi - lo, lo);
+}
+
+// The four-colour relaxation of one node, the same arithmetic as the sweep
+// kernel (gs_target with the lane share of each side written out): the E-
+// and W-side shares fma(0.25, NE + SE, E) and fma(0.25, NW + SW, W) summed,
+// then psi <- psi + w (g - psi).
+template <typename T>
+__device__ __forceinline__ T mg_relax_at(const T* psi, const T* F, size_t p, int pitch, T w) {
+  const T qe = fma_t(T(0.25), psi[p + pitch + 1] + psi[p - pitch + 1], psi[p + 1]);
+  const T qw = fma_t(T(0.25), psi[p + pitch - 1] + psi[p - pitch - 1], psi[p - 1]);
+  const T g = fma_t(T(0.2), (qe + qw) + (psi[p + pitch] + psi[p - pitch]), F[p]);
+  const T v = psi[p];
+  return fma_t(w, g - v, v);
+}
+
 // r = (g - psi) / (0.3 h^2): the residual of the compact equation in
 // vorticity units (zero on walls).
 template <typename T>
@@ -1218,10 +1324,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_residual(const T* __restrict__ ps
     r[p] = T(0);
     return;
   }
-  const T s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pitch] + psi[p - pitch]);
-  const T sd = (psi[p + pitch + 1] + psi[p + pitch - 1]) + (psi[p - pitch + 1] + psi[p - pitch - 1]);
-  const T g = fma_t(T(0.2), s4, fma_t(T(0.05), sd, F[p]));
-  r[p] = (g - psi[p]) * inv03h2;
+  r[p] = mg_residual_at(psi, F, p, pitch, inv03h2);
 }
 
 // Coarse right-hand side F_c = 0.3 h_c^2 R r and a zero coarse iterate (both
@@ -1244,26 +1347,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(const T* __restrict__ r,
     Fc[pc] = T(0);
     return;
   }
-  const long long mf = nf - 1, mc = nc - 1;
-  const int i0 = max(1, (int)(((I - 1) * mf) / mc) + 1);
-  const int i1 = min(nf - 2, (int)(((I + 1) * mf + mc - 1) / mc) - 1);
-  const int j0 = max(1, (int)(((J - 1) * mf) / mc) + 1);
-  const int j1 = min(nf - 2, (int)(((J + 1) * mf + mc - 1) / mc) - 1);
-  const T invmf = T(1) / (T)mf;
-  T sum = T(0);
-  for (int j = j0; j <= j1; ++j) {
-    const long long dj = (long long)j * mc - (long long)J * mf;
-    const T wy = (T)(mf - (dj < 0 ? -dj : dj)) * invmf;
-    if (wy <= T(0)) continue;
-    T row = T(0);
-    for (int i = i0; i <= i1; ++i) {
-      const long long di = (long long)i * mc - (long long)I * mf;
-      const T wx = (T)(mf - (di < 0 ? -di : di)) * invmf;
-      if (wx > T(0)) row = fma_t(wx, r[(size_t)j * pitchf + i], row);
-    }
-    sum = fma_t(wy, row, sum);
-  }
-  Fc[pc] = scale * sum;
+  Fc[pc] = scale * mg_restrict_at(r, nf, pitchf, nc, I, J);
 }
 
 // psi_f += P E_c (bilinear interpolation of the coarse correction).
@@ -1276,15 +1360,120 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(const T* __restrict__ Ec,
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i < 1 || j < 1 || i > nf - 2 || j > nf - 2) return;
-  const long long mf = nf - 1, mc = nc - 1;
-  const int I = (int)(((long long)i * mc) / mf);
-  const int J = (int)(((long long)j * mc) / mf);
-  const T ti = (T)((long long)i * mc - (long long)I * mf) / (T)mf;
-  const T tj = (T)((long long)j * mc - (long long)J * mf) / (T)mf;
-  const size_t c = (size_t)J * pitchc + I;
-  const T lo = fma_t(ti, Ec[c + 1] - Ec[c], Ec[c]);
-  const T hi = fma_t(ti, Ec[c + pitchc + 1] - Ec[c + pitchc], Ec[c + pitchc]);
-  psi[(size_t)j * pitchf + i] += fma_t(tj, hi - lo, lo);
+  psi[(size_t)j * pitchf + i] += mg_prolong_at(Ec, nc, pitchc, nf, i, j);
+}
+
+// ---------------------------------------------------------------------------
+// The coarse end of a V-cycle in one block: every level from the first one
+// with at most kMgFuseMax nodes a side down to the coarsest and back, with
+// all iterates, right-hand sides and residuals in LDS (dense, pitch n).  On
+// these grids a per-level launch does almost no work, so the launches'
+// fixed cost was most of a V-cycle's time; here the levels are separated by
+// block barriers instead.  Each step is the per-level kernels' arithmetic
+// (shared device functions) and the relaxation sweeps update the colours in
+// place in the same order as the sweep kernel, so the cycle gives the same
+// bits as the per-level launches.  F of the first level is read from its
+// global array, its iterate E read and written back there (walls stay 0).
+// ---------------------------------------------------------------------------
+constexpr int kMgFuseMax = 65;
+constexpr int kMgFuseThreads = 256;
+constexpr int kMgFuseLevels = 6;
+// nodes of every level below a 65-node level (65, 33, 17, 9), each level
+// holding E, F and the residual: 3 x 5684 values (136 KiB in FP64)
+constexpr int kMgFuseNodes = 65 * 65 + 33 * 33 + 17 * 17 + 9 * 9;
+
+struct MgFusedArgs {
+  int levels;                     // levels in the block, finest first
+  int n[kMgFuseLevels];           // nodes per side
+  double inv03h2[kMgFuseLevels];  // residual scale 1 / (0.3 h^2)
+  double scale[kMgFuseLevels];    // restriction scale onto level l (l >= 1)
+  int nu;                         // sweeps before and after the coarse correction
+  int coarse_sweeps;
+  double coarse_relax;
+};
+
+template <typename T>
+__device__ __forceinline__ void mg_block_sweeps(T* E, const T* F, int n, int sweeps, T w) {
+  for (int s = 0; s < sweeps; ++s) {
+    for (int c = 0; c < 4; ++c) {
+      const int cx = c & 1, cy = c >> 1;
+      // the interior nodes of parity (cx, cy): i = i0, i0 + 2, ... <= n - 2
+      const int i0 = cx == 0 ? 2 : 1, j0 = cy == 0 ? 2 : 1;
+      const int nx = (n - 2 - i0) / 2 + 1, ny = (n - 2 - j0) / 2 + 1;
+      for (int q = threadIdx.x; q < nx * ny; q += kMgFuseThreads) {
+        const int j = j0 + 2 * (q / nx), i = i0 + 2 * (q - (q / nx) * nx);
+        const size_t p = (size_t)j * n + i;
+        E[p] = mg_relax_at(E, F, p, n, w);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMgFuseThreads) void k_mg_fused(T* __restrict__ Eg,
+                                                             const T* __restrict__ Fg, int pitch,
+                                                             MgFusedArgs a,
+                                                             const PoissonCtl* __restrict__ ctl) {
+  __shared__ T mg_lds[3 * kMgFuseNodes];
+  if (ctl->state != SOLVE_RUN) return;
+  T* E[kMgFuseLevels];
+  T* F[kMgFuseLevels];
+  T* R[kMgFuseLevels];
+  {
+    T* cur = mg_lds;
+    for (int l = 0; l < a.levels; ++l) {
+      const int sz = a.n[l] * a.n[l];
+      E[l] = cur;
+      F[l] = cur + sz;
+      R[l] = cur + 2 * sz;
+      cur += 3 * sz;
+    }
+  }
+  const int n0 = a.n[0];
+  for (int q = threadIdx.x; q < n0 * n0; q += kMgFuseThreads) {
+    const int j = q / n0, i = q - j * n0;
+    E[0][q] = Eg[(size_t)j * pitch + i];
+    F[0][q] = Fg[(size_t)j * pitch + i];
+  }
+  __syncthreads();
+  const int L = a.levels - 1;
+  for (int l = 0; l < L; ++l) {
+    const int n = a.n[l], nc = a.n[l + 1];
+    mg_block_sweeps(E[l], F[l], n, a.nu, T(1.0));
+    const T inv = (T)a.inv03h2[l];
+    for (int q = threadIdx.x; q < n * n; q += kMgFuseThreads) {
+      const int j = q / n, i = q - j * n;
+      R[l][q] = (i == 0 || j == 0 || i == n - 1 || j == n - 1)
+                    ? T(0)
+                    : mg_residual_at(E[l], F[l], (size_t)q, n, inv);
+    }
+    __syncthreads();
+    const T sc = (T)a.scale[l + 1];
+    for (int q = threadIdx.x; q < nc * nc; q += kMgFuseThreads) {
+      const int J = q / nc, I = q - J * nc;
+      E[l + 1][q] = T(0);
+      F[l + 1][q] = (I == 0 || J == 0 || I == nc - 1 || J == nc - 1)
+                        ? T(0)
+                        : sc * mg_restrict_at(R[l], n, n, nc, I, J);
+    }
+    __syncthreads();
+  }
+  mg_block_sweeps(E[L], F[L], a.n[L], a.coarse_sweeps, (T)a.coarse_relax);
+  for (int l = L - 1; l >= 0; --l) {
+    const int n = a.n[l], nc = a.n[l + 1];
+    for (int q = threadIdx.x; q < n * n; q += kMgFuseThreads) {
+      const int j = q / n, i = q - j * n;
+      if (i >= 1 && j >= 1 && i <= n - 2 && j <= n - 2)
+        E[l][q] += mg_prolong_at(E[l + 1], nc, nc, n, i, j);
+    }
+    __syncthreads();
+    mg_block_sweeps(E[l], F[l], n, a.nu, T(1.0));
+  }
+  for (int q = threadIdx.x; q < n0 * n0; q += kMgFuseThreads) {
+    const int j = q / n0, i = q - j * n0;
+    if (i >= 1 && j >= 1 && i <= n0 - 2 && j <= n0 - 2) Eg[(size_t)j * pitch + i] = E[0][q];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1389,7 +1578,8 @@ __global__ __launch_bounds__(kBlock) void k_thom(const double* __restrict__ psi,
 // Control-block reset and the mixed-precision refinement kernels.
 // ---------------------------------------------------------------------------
 __global__ void k_ctl_reset(PoissonCtl* c, double relax, double tol_hat, long long max_sweeps,
-                            long long stall_window, long long sweeps_per_check) {
+                            long long stall_window, long long sweeps_per_check,
+                            double floor_ulps) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   c->state = SOLVE_RUN;
   c->phase = 0;
@@ -1405,6 +1595,7 @@ __global__ void k_ctl_reset(PoissonCtl* c, double relax, double tol_hat, long lo
   c->max_sweeps = max_sweeps;
   c->stall_window = stall_window;
   c->sweeps_per_check = sweeps_per_check;
+  c->floor_ulps = floor_ulps;
   c->floor_limited = 0;
   c->werror = 0;
 }
@@ -1726,9 +1917,10 @@ hipError_t launch_stage(const double* psi, const float* psi32, const double* w0,
 }
 
 hipError_t launch_ctl_reset(PoissonCtl* ctl, double relax, double tol_hat, long long max_sweeps,
-                            long long stall_window, long long sweeps_per_check, hipStream_t st) {
+                            long long stall_window, long long sweeps_per_check, hipStream_t st,
+                            double floor_ulps) {
   hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, ctl, relax, tol_hat, max_sweeps,
-                     stall_window, sweeps_per_check);
+                     stall_window, sweeps_per_check, floor_ulps);
   return hipGetLastError();
 }
 
@@ -1902,6 +2094,44 @@ hipError_t launch_mg_prolong(const double* Ec, int nc, int pitchc, double* psi, 
 hipError_t launch_mg_prolong(const float* Ec, int nc, int pitchc, float* psi, int nf, int pitchf,
                              const PoissonCtl* ctl, hipStream_t st) {
   return mg_prolong<float>(Ec, nc, pitchc, psi, nf, pitchf, ctl, st);
+}
+
+template <typename T>
+hipError_t mg_fused(T* E, const T* F, int pitch, const int* n, int levels, int nu,
+                    int coarse_sweeps, double coarse_relax, const PoissonCtl* ctl, hipStream_t st) {
+  if (levels < 1 || levels > kMgFuseLevels || n[0] > kMgFuseMax) return hipErrorInvalidValue;
+  MgFusedArgs a{};
+  a.levels = levels;
+  int nodes = 0;
+  for (int l = 0; l < levels; ++l) {
+    a.n[l] = n[l];
+    const double h = 1.0 / (n[l] - 1);
+    a.inv03h2[l] = 1.0 / (0.3 * h * h);
+    if (l > 0) {
+      const double ratio = (double)(n[l] - 1) / (double)(n[l - 1] - 1);
+      a.scale[l] = 0.3 * h * h * ratio * ratio;
+    }
+    nodes += n[l] * n[l];
+  }
+  a.nu = nu;
+  a.coarse_sweeps = coarse_sweeps;
+  a.coarse_relax = coarse_relax;
+  if (nodes > kMgFuseNodes) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mg_fused<T>, dim3(1), dim3(kMgFuseThreads), 0, st, E, F, pitch, a, ctl);
+  return hipGetLastError();
+}
+
+int mg_fuse_max() { return kMgFuseMax; }
+
+hipError_t launch_mg_fused(double* E, const double* F, int pitch, const int* n, int levels,
+                           int nu, int coarse_sweeps, double coarse_relax, const PoissonCtl* ctl,
+                           hipStream_t st) {
+  return mg_fused<double>(E, F, pitch, n, levels, nu, coarse_sweeps, coarse_relax, ctl, st);
+}
+hipError_t launch_mg_fused(float* E, const float* F, int pitch, const int* n, int levels, int nu,
+                           int coarse_sweeps, double coarse_relax, const PoissonCtl* ctl,
+                           hipStream_t st) {
+  return mg_fused<float>(E, F, pitch, n, levels, nu, coarse_sweeps, coarse_relax, ctl, st);
 }
 
 hipError_t launch_sor64_relax(const SorConfig& cfg, const double* psi_in, double* psi_out,

@@ -439,6 +439,14 @@ cav::SorConfig mg_cfg(int n) {
   return cav::SorConfig{64, 32, 2, 512, 0};
 }
 constexpr int kMgNu = 2;   // pre- and post-smoothing sweeps (one launch each)
+// A multigrid solve stops (floor-limited) once the residual max-norm, in the
+// units of the relaxation (g - psi), is within this many ulps of max |psi|:
+// the FP64 residual of the exact discrete solution sits at 2.6-3.9 ulps
+// (1024^2), so cycles beyond this change only rounding noise.  With the
+// developed flows of long runs (|psi| ~ 0.1 at 1024^2) that floor lies above
+// a 1e-10 tolerance, and without this test every solve ran until its stall
+// window (eight cycles without halving) ran out.
+constexpr double kMgFloorUlps = 8.0;
 
 // ---------------------------------------------------------------------------
 // Poisson solves.  All members listed in `idx` are solved together: their
@@ -452,9 +460,12 @@ int reset_ctl(cavity_s* h, Member& m) {
   const double tol_hat = m.tol * 0.3 * m.h * m.h;  // (g - psi) = (3 h^2 / 10) r
   const long long spc = unit_sweeps(m);
   // multigrid halves the residual every cycle until the rounding floor:
-  // eight cycles without halving mean the floor
-  const long long stall = m.solver == CAVITY_SOLVER_MG ? 8LL * spc : m.stall_window;
-  HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, stall, spc, h->st));
+  // eight cycles without halving mean the floor, and a residual within
+  // kMgFloorUlps ulps of max |psi| is the floor itself
+  const bool mg = m.solver == CAVITY_SOLVER_MG;
+  const long long stall = mg ? 8LL * spc : m.stall_window;
+  HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, stall, spc, h->st,
+                                   mg ? kMgFloorUlps : 0.0));
   return CAVITY_OK;
 }
 
@@ -466,16 +477,21 @@ long long unit_sweeps(const Member& m) {
 }
 
 // One V(2,2)-cycle of the compact equation for member m, starting and ending
-// with the iterate in m.psi.  Each smoothing step is one launch of two
-// four-colour Gauss-Seidel sweeps from one buffer of the level to the other,
-// so after pre- and post-smoothing a level's iterate is back in its first
-// buffer; the coarsest level takes an even number of launches.
+// with the iterate in m.psi.  On the finer levels each smoothing step is one
+// launch of two four-colour Gauss-Seidel sweeps from one buffer of the level
+// to the other, so after pre- and post-smoothing a level's iterate is back in
+// its first buffer; the levels from the first with at most 65 nodes a side
+// down to the coarsest run in one block (launch_mg_fused), with the same
+// arithmetic.
 int enqueue_vcycle(cavity_s* h, Member& m) {
   const int L = (int)m.mg.size() - 1;
   auto E = [&](int l) { return l == 0 ? m.psi : m.mg[l].E; };
   auto Eb = [&](int l) { return l == 0 ? m.psi_b : m.mg[l].Eb; };
   auto Fp = [&](int l) { return l == 0 ? m.F : m.mg[l].F; };
-  for (int l = 0; l < L; ++l) {
+  // levels lc..L run in one block (the coarse end of the cycle)
+  int lc = 0;
+  while (lc < L && m.mg[lc].n > cav::mg_fuse_max()) ++lc;
+  for (int l = 0; l < lc; ++l) {
     const MgLevel& v = m.mg[l];
     const MgLevel& c = m.mg[l + 1];
     HIP_TRY(h, cav::launch_sor64_relax(mg_cfg(v.n), E(l), Eb(l), Fp(l), v.n, v.pitch, m.ctl, 1.0,
@@ -485,16 +501,12 @@ int enqueue_vcycle(cavity_s* h, Member& m) {
                                        h->st));
   }
   {
-    const MgLevel& c = m.mg[L];
-    const cav::SorConfig cc = mg_cfg(c.n);
-    for (int k = 0; k < kMgCoarseSweeps / (2 * cc.s); ++k) {
-      HIP_TRY(h, cav::launch_sor64_relax(cc, E(L), Eb(L), Fp(L), c.n, c.pitch, m.ctl,
-                                         kMgCoarseRelax, h->st));
-      HIP_TRY(h, cav::launch_sor64_relax(cc, Eb(L), E(L), Fp(L), c.n, c.pitch, m.ctl,
-                                         kMgCoarseRelax, h->st));
-    }
+    int ns[8];
+    for (int l = lc; l <= L; ++l) ns[l - lc] = m.mg[l].n;
+    HIP_TRY(h, cav::launch_mg_fused(E(lc), Fp(lc), m.mg[lc].pitch, ns, L - lc + 1, kMgNu,
+                                    kMgCoarseSweeps, kMgCoarseRelax, m.ctl, h->st));
   }
-  for (int l = L - 1; l >= 0; --l) {
+  for (int l = lc - 1; l >= 0; --l) {
     const MgLevel& v = m.mg[l];
     const MgLevel& c = m.mg[l + 1];
     HIP_TRY(h, cav::launch_mg_prolong(E(l + 1), c.n, c.pitch, Eb(l), v.n, v.pitch, m.ctl, h->st));
@@ -504,14 +516,13 @@ int enqueue_vcycle(cavity_s* h, Member& m) {
   return CAVITY_OK;
 }
 
-// One chunk of work for member m: `units` check groups (FP64: pairs_per_check
-// launch pairs, the last launch checking) or refinement rounds (mixed).
-// Every launch returns at once once the solve has stopped.
 // The same cycle in FP32 for the correction equation of mixed precision:
 // d32a holds the correction, R32 the FP64 residual rounded to FP32.
 int enqueue_vcycle32(cavity_s* h, Member& m) {
   const int L = (int)m.mg32.size() - 1;
-  for (int l = 0; l < L; ++l) {
+  int lc = 0;
+  while (lc < L && m.mg32[lc].n > cav::mg_fuse_max()) ++lc;
+  for (int l = 0; l < lc; ++l) {
     const MgLevel32& v = m.mg32[l];
     const MgLevel32& c = m.mg32[l + 1];
     HIP_TRY(h, cav::launch_sor32(mg_cfg(v.n), v.E, v.Eb, v.F, v.n, v.pitch, m.ctl, 1.0, h->st));
@@ -520,16 +531,12 @@ int enqueue_vcycle32(cavity_s* h, Member& m) {
                                        h->st));
   }
   {
-    const MgLevel32& c = m.mg32[L];
-    const cav::SorConfig cc = mg_cfg(c.n);
-    for (int k = 0; k < kMgCoarseSweeps / (2 * cc.s); ++k) {
-      HIP_TRY(h, cav::launch_sor32(cc, c.E, c.Eb, c.F, c.n, c.pitch, m.ctl, kMgCoarseRelax,
-                                   h->st));
-      HIP_TRY(h, cav::launch_sor32(cc, c.Eb, c.E, c.F, c.n, c.pitch, m.ctl, kMgCoarseRelax,
-                                   h->st));
-    }
+    int ns[8];
+    for (int l = lc; l <= L; ++l) ns[l - lc] = m.mg32[l].n;
+    HIP_TRY(h, cav::launch_mg_fused(m.mg32[lc].E, m.mg32[lc].F, m.mg32[lc].pitch, ns, L - lc + 1,
+                                    kMgNu, kMgCoarseSweeps, kMgCoarseRelax, m.ctl, h->st));
   }
-  for (int l = L - 1; l >= 0; --l) {
+  for (int l = lc - 1; l >= 0; --l) {
     const MgLevel32& v = m.mg32[l];
     const MgLevel32& c = m.mg32[l + 1];
     HIP_TRY(h, cav::launch_mg_prolong(c.E, c.n, c.pitch, v.Eb, v.n, v.pitch, m.ctl, h->st));
@@ -538,6 +545,9 @@ int enqueue_vcycle32(cavity_s* h, Member& m) {
   return CAVITY_OK;
 }
 
+// One chunk of work for member m: `units` check groups (FP64: pairs_per_check
+// launch pairs, the last launch checking) or refinement rounds (mixed).
+// Every launch returns at once once the solve has stopped.
 int enqueue_chunk(cavity_s* h, Member& m, int units) {
   for (int u = 0; u < units; ++u) {
     if (m.solver == CAVITY_SOLVER_MG && m.mixed) {
