@@ -499,6 +499,64 @@ __device__ __forceinline__ void rhs_to_regs(const T* __restrict__ F, int n, int 
   }
 }
 
+// psi of the owned nodes straight into registers, one pair load per lane and
+// row as for F (coalesced along x: a wavefront reads one plane row pair of
+// the region); nodes outside the grid, and the node beyond an odd grid's last
+// column, are 0.  COHERENT loads carry the device-scope bit (persistent
+// kernels, whose tiles other blocks wrote in this launch).
+template <typename T, int TX, int TY, int S, int NT, int HX, bool COHERENT>
+__device__ __forceinline__ void psi_to_regs(const T* __restrict__ pin, int n, int pitch, int x0,
+                                            int y0, int lane, int b0,
+                                            T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K]) {
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
+  using T2 = typename Pair<T>::type;
+  static_assert(!COHERENT || std::is_same<T, double>::value, "coherent tiles are FP64");
+  const __amdgpu_buffer_rsrc_t crs = coh_buffer(pin, (size_t)n * pitch * sizeof(T));
+  const int gx = x0 + 2 * lane;
+#pragma unroll
+  for (int cy = 0; cy < 2; ++cy) {
+#pragma unroll
+    for (int r = 0; r < G::K; ++r) {
+      const int gy = y0 + 2 * (b0 + r) + cy;
+      T2 f;
+      f.x = f.y = T(0);
+      if (lane < G::RXH && b0 + r < G::RYH && (unsigned)gy < (unsigned)n &&
+          (unsigned)gx < (unsigned)n) {
+        const size_t g = (size_t)gy * pitch + gx;
+        if constexpr (COHERENT)
+          f = coh_load_pair(crs, g);
+        else
+          f = *reinterpret_cast<const T2*>(pin + g);
+      }
+      pv[2 * cy][r] = f.x;
+      pv[2 * cy + 1][r] = f.y;
+    }
+  }
+}
+
+// The rows of a strip that the neighbouring strips read before any pass has
+// published them: its last row of the y-parity-1 planes (read by the strip
+// above in passes 0 and 1) and its first row of the y-parity-0 planes (read
+// by the strip below in passes 2 and 3).  Rows that no pass ever updates (a
+// wall, nodes outside the grid) keep these values.
+template <typename T, int TX, int TY, int S, int NT, int HX>
+__device__ __forceinline__ void publish_strip_edges(T* pl, int lane, int b0,
+                                                    const T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K]) {
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
+  constexpr int K = G::K;
+  if (lane >= G::RXH) return;  // lanes beyond a plane row own no node
+  if (b0 + K - 1 < G::RYH) {
+    const int o = (b0 + K - 1) * G::RXH + lane;
+    pl[2 * G::PLANE + o] = pv[2][K - 1];
+    pl[3 * G::PLANE + o] = pv[3][K - 1];
+  }
+  if (b0 < G::RYH) {
+    const int o = b0 * G::RXH + lane;
+    pl[o] = pv[0][0];
+    pl[G::PLANE + o] = pv[1][0];
+  }
+}
+
 // The right-hand side of the node beyond an odd grid (x = n, in the pitch
 // padding) to 0.  Called once the following loads are issued too: using the
 // values earlier would make those loads wait.
@@ -657,14 +715,22 @@ __device__ __forceinline__ bool sor_tile(const T* __restrict__ pin, T* __restric
   const int b0 = wave * K;         // first owned row of every plane
   T fv[4][K];
   T pv[4][K];
-  // F first: its loads are in flight while those of psi are issued, and the
-  // wait for psi before its LDS stores covers both
+  // F and psi of the owned nodes straight into registers (all loads in
+  // flight before the first use); only the strip edges the neighbouring
+  // strips read go through LDS
   rhs_to_regs<T, TX, TY, S, NT, HX>(F, n, pitch, x0, y0, lane, b0, fv);
-  region_to_lds<T, TX, TY, S, NT, HX, false, 0, COH>(pin, n, pitch, x0, y0, pl, tid);
+  psi_to_regs<T, TX, TY, S, NT, HX, COH>(pin, n, pitch, x0, y0, lane, b0, pv);
   rhs_zero_beyond<T, TX, TY, S, NT, HX>(n, x0, lane, fv);
+  if (x0 + 2 * lane + 1 >= n) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      pv[1][r] = T(0);
+      pv[3][r] = T(0);
+    }
+  }
+  publish_strip_edges<T, TX, TY, S, NT, HX>(pl, lane, b0, pv);
   __syncthreads();
   if (!run) return false;
-  lds_to_regs<T, TX, TY, S, NT, HX, false>(pl, lane, b0, pv);
   const int lxd0 = 1 - x0, lxd1 = n - 2 - x0;  // domain interior in local coordinates
   const int lyd0 = 1 - y0, lyd1 = n - 2 - y0;
   // Every LDS and scalar read issued so far has arrived before the passes
