@@ -715,22 +715,34 @@ __device__ __forceinline__ bool sor_tile(const T* __restrict__ pin, T* __restric
   const int b0 = wave * K;         // first owned row of every plane
   T fv[4][K];
   T pv[4][K];
-  // F and psi of the owned nodes straight into registers (all loads in
-  // flight before the first use); only the strip edges the neighbouring
-  // strips read go through LDS
   rhs_to_regs<T, TX, TY, S, NT, HX>(F, n, pitch, x0, y0, lane, b0, fv);
-  psi_to_regs<T, TX, TY, S, NT, HX, COH>(pin, n, pitch, x0, y0, lane, b0, pv);
-  rhs_zero_beyond<T, TX, TY, S, NT, HX>(n, x0, lane, fv);
-  if (x0 + 2 * lane + 1 >= n) {
+  if constexpr (std::is_same<T, double>::value) {
+    // FP64: psi of the owned nodes straight into registers (all loads in
+    // flight before the first use); only the strip edges the neighbouring
+    // strips read go through LDS (measured: 146 -> 120 us per launch of the
+    // 4096^2 sweep, unchanged at 1024^2)
+    psi_to_regs<T, TX, TY, S, NT, HX, COH>(pin, n, pitch, x0, y0, lane, b0, pv);
+    rhs_zero_beyond<T, TX, TY, S, NT, HX>(n, x0, lane, fv);
+    if (x0 + 2 * lane + 1 >= n) {
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-      pv[1][r] = T(0);
-      pv[3][r] = T(0);
+      for (int r = 0; r < K; ++r) {
+        pv[1][r] = T(0);
+        pv[3][r] = T(0);
+      }
     }
+    publish_strip_edges<T, TX, TY, S, NT, HX>(pl, lane, b0, pv);
+    __syncthreads();
+    if (!run) return false;
+  } else {
+    // FP32: the region through LDS (measured 4 % faster than the direct
+    // loads at 1024^2 and 4096^2: 11.4 against 11.8 us, 98.7 against
+    // 103.7 us per launch)
+    region_to_lds<T, TX, TY, S, NT, HX, false, 0, COH>(pin, n, pitch, x0, y0, pl, tid);
+    rhs_zero_beyond<T, TX, TY, S, NT, HX>(n, x0, lane, fv);
+    __syncthreads();
+    if (!run) return false;
+    lds_to_regs<T, TX, TY, S, NT, HX, false>(pl, lane, b0, pv);
   }
-  publish_strip_edges<T, TX, TY, S, NT, HX>(pl, lane, b0, pv);
-  __syncthreads();
-  if (!run) return false;
   const int lxd0 = 1 - x0, lxd1 = n - 2 - x0;  // domain interior in local coordinates
   const int lyd0 = 1 - y0, lyd1 = n - 2 - y0;
   // Every LDS and scalar read issued so far has arrived before the passes

@@ -1500,12 +1500,15 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
     m.sweeps_total = 0;
     m.sweeps_step = 0;
   }
-  // Batch defaults: the FP64 tile shape that measured fastest; residual
-  // checks every 32 sweeps; FP32 rounds as long as the largest member's.
+  // Batch defaults: the tile shapes the autotuner measured fastest; residual
+  // checks every 30-32 sweeps; FP32 rounds as long as the largest member's.
   // Cavities of at most 512 nodes a side (the ones graph execution is the
   // default for) take 64 x 32 tiles with 4 sweeps per round and 512 threads:
   // sixteen 128^2 cavities 25.5 Mcell-steps/s against 21.0 with 64 x 64 tiles
-  // of 768 threads, which stay the fastest for larger cavities.
+  // of 768 threads.  Larger ones take the per-launch kernel's tiles, five
+  // sweeps per round (fewer grid barriers per sweep): the six-cavity
+  // Reynolds sweep 16.9 Mcell-steps/s in FP64 against 13.6 with 64 x 64
+  // tiles and three sweeps per round.
   {
     int inner = 0, nmax = 0;
     for (const Member& m : h->m) {
@@ -1515,8 +1518,10 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
     const int small = h->m[0].n <= 320 && count == 1;
     h->bcfg64 = small           ? cav::SorConfig{32, 32, 1, 256, 0}
                 : nmax <= 512 ? cav::SorConfig{64, 32, 4, 512, 0}
-                              : cav::SorConfig{64, 64, 3, 768, 0};
-    h->bcfg32 = small ? cav::SorConfig{32, 32, 1, 256, 0} : cav::SorConfig{64, 64, 4, 1024, 0};
+                              : cav::SorConfig{84, 54, 5, 1024, 0};
+    h->bcfg32 = small         ? cav::SorConfig{32, 32, 1, 256, 0}
+                : nmax <= 512 ? cav::SorConfig{64, 64, 4, 1024, 0}
+                              : cav::SorConfig{88, 56, 5, 1024, 0};
     h->b_ppc = std::max(1, 32 / (2 * h->bcfg64.s));
     h->b_inner_pairs = std::max(1, (inner + 2 * h->bcfg32.s - 1) / (2 * h->bcfg32.s));
   }

@@ -13,6 +13,9 @@ from oracle.cavity_oracle import CavityOracle
 
 pytestmark = pytest.mark.gpu
 
+# a compiled per-launch FP64 sweep kernel for each number of sweeps per launch
+SOLO_TILES = {1: (32, 32, 256), 2: (64, 64, 1024), 3: (64, 64, 1024), 4: (64, 64, 512),
+              5: (84, 54, 1024)}
 SMALL4 = [(5000.0, 130), (10000.0, 257), (15000.0, 384), (20000.0, 512)]
 SWEEP6 = [(5000.0, 256), (10000.0, 512), (15000.0, 768), (20000.0, 1024), (25000.0, 1024),
           (30000.0, 1024)]
@@ -99,9 +102,10 @@ def test_batch_default_tuning_bitwise_equals_solo(cm, members, mode, precision):
     """The batch's own default tuning (tiles, sweeps per round, check spacing,
     FP32 rounds), each member stopping on its own: on cavities of 130 to 512
     nodes a side (64 x 32 tiles, four sweeps per round) and on the six-cavity
-    Reynolds sweep (64 x 64 tiles; 992 tiles, more than the co-resident grid,
-    so blocks take several tiles per round), every step of every member
-    equals the same cavity run alone with the same sweep schedule, bitwise."""
+    Reynolds sweep (84 x 54 tiles, five sweeps per round; 981 tiles on a
+    co-resident grid of one block per CU, so blocks take several tiles per
+    round), every step of every member equals the same cavity run alone with
+    the same sweep schedule, bitwise."""
     steps = 3
     print(f"[batch default {mode} precision={precision}] {members}", flush=True)
     c = cm.Cavity([cm.Params(n=n, re=re, precision=precision) for re, n in members])
@@ -116,8 +120,8 @@ def test_batch_default_tuning_bitwise_equals_solo(cm, members, mode, precision):
         t = s.tuning()
         # the results do not depend on the tile shape, only on the sweeps per
         # check (FP64) or per refinement round (mixed) and the relaxation
-        s.set_tuning(tile_x=64, tile_y=64, sweeps_per_launch=bt["sweeps_per_launch"],
-                     threads=512 if bt["sweeps_per_launch"] == 4 else 1024,
+        tx, ty, nt = SOLO_TILES[bt["sweeps_per_launch"]]
+        s.set_tuning(tile_x=tx, tile_y=ty, sweeps_per_launch=bt["sweeps_per_launch"], threads=nt,
                      tile_x32=bt["tile_x32"], tile_y32=bt["tile_y32"],
                      sweeps_per_launch32=bt["sweeps_per_launch32"], threads32=bt["threads32"],
                      check_every=bt["check_every"], inner_sweeps=bt["inner_sweeps"],
