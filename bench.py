@@ -1,7 +1,8 @@
 """Throughput of the driven-lid-cavity time step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--exec stream|persistent|graph] [--no-cpu] [--no-extras]
+                    [--exec stream|persistent|graph|resident] [--solver sor|multigrid]
+                    [--warm-start L] [--no-cpu] [--no-extras | --extras KEY,...]
 
 A step is one SSPRK(5,4) step of the whole hot path (five stages, each with
 transport RHS + stage combination, compact-Poisson SOR solve to tolerance,
@@ -11,7 +12,7 @@ relaxation (four-colour SOR).  Inputs are resident in HBM when timing starts.
 Extras (same JSON line): the same workload with the multigrid solver and in
 persistent execution; the 1024 x 1024 Re = 3e4 cavity in FP64 and in mixed
 precision (same steps); the 4096 x 4096 Re = 3e4 noise-start cavity (FP64 SOR
-and mixed SOR for the same step, with the rooflines of both sweep kernels at
+and mixed SOR for the same two steps after one warm-up step, with the rooflines of both sweep kernels at
 that size, and FP64 multigrid); the six-cavity Reynolds sweep (256^2 ...
 1024^2) batched in one persistent launch per stage (hipGraph, tile shape from
 the autotuner) vs the same cavities run one by one.  Prints one JSON line.
@@ -40,21 +41,28 @@ EXEC = {"stream": 0, "persistent": 1, "graph": 2, "resident": 3}
 
 
 def _kernel_source_hash() -> str:
-    """Hash of the kernel source's code: comments, blank lines and trailing
-    blanks are left out, so that only a change to the code invalidates the
+    """Hash of the code a sweep launch runs: the kernel source up to the end
+    of the sweep kernel's definition (everything it can refer to) and its
+    tile-configuration dispatch, with comments, blank lines and trailing
+    blanks left out, so that only a change to that code invalidates the
     recorded counters (the file has no string literal holding a comment
     marker)."""
     path = os.path.join(ROOT, "paper_0809_3098_amd", "csrc", "cavity_kernels.hip")
     with open(path, encoding="utf-8") as f:
-        text = f.read()
+        lines = f.read().splitlines()
+    k = next(i for i, ln in enumerate(lines) if "void k_sor(" in ln)
+    end_a = next(i for i in range(k, len(lines)) if lines[i] == "}")
+    b = next(i for i, ln in enumerate(lines) if ln.startswith("hipError_t sor_launch(")) - 1
+    end_b = next(i for i in range(b, len(lines)) if lines[i].startswith("}  // namespace"))
+    text = "\n".join(lines[:end_a + 1] + lines[b:end_b + 1])
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
-    code = "\n".join(ln for ln in lines if ln)
-    return hashlib.sha256(code.encode()).hexdigest()[:16]
+    code = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+    return hashlib.sha256("\n".join(ln for ln in code if ln).encode()).hexdigest()[:16]
 
 
 def _traffic(key: str):
-    """HBM bytes per sweep launch from committed PMC counters, if still valid."""
+    """L2-miss bytes per sweep launch from committed PMC counters, if the sweep
+    kernel's code is still the one they were taken on."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f).get(key)
@@ -62,7 +70,7 @@ def _traffic(key: str):
         return None
     if not rec or rec.get("kernel_source_sha256_16") != _kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("l2miss_bytes_per_launch")
 
 
 def _cpu_baseline(n, re, steps):
@@ -142,20 +150,29 @@ def _sweep_roofline(torch, cav, stream, launches, arith, key):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cavity1024_re1e4_fp64")
     ap.add_argument("--exec", default="stream", choices=sorted(EXEC))
+    ap.add_argument("--warm-start", type=int, default=0,
+                    help="start of each stage's solve: 0 default, 1 the previous stage's "
+                         "psi, 2..8 extrapolation through that many steps")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="override the workload's precision (the headline run only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed and batched lines")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated subset of the extra lines: multigrid, persistent, "
+                         "resident, re3e4, n4096, coupled, re_sweep6_fp64, re_sweep6_mixed, "
+                         "re_scan16_small_fp64 (default all)")
+    ap.add_argument("--solver", default="sor", choices=["sor", "multigrid"],
+                    help="Poisson solver of the headline workload")
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--relax-launches", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a cold 1 GiB device copy (torch), the known-size kernel the "
                          "HBM counters of a profiling run are scaled by")
-    ap.add_argument("--extra-steps", type=int, default=5)
+    ap.add_argument("--extra-steps", type=int, default=10)
     ap.add_argument("--tune-cache", default=None,
                     help="JSON-lines cache of the autotuner (default: none, tune every run)")
     ap.add_argument("--log-run", default=None, metavar="JSONL",
@@ -186,8 +203,9 @@ def main():
 
     import torch
     from paper_0809_3098_amd import inputs
-    from paper_0809_3098_amd.cavity import (CAVITY_FP64, CAVITY_MIXED, CAVITY_SOLVER_MG, Cavity,
-                                            Params)
+    from paper_0809_3098_amd.cavity import (CAVITY_FP64, CAVITY_MIXED, CAVITY_SOLVER_MG,
+                                            CAVITY_WARM_LEVELS_FP64, CAVITY_WARM_LEVELS_MIXED,
+                                            Cavity, Params)
     from paper_0809_3098_amd.workloads import WORKLOADS
 
     dev = torch.device("cuda:0")
@@ -295,7 +313,8 @@ def main():
         omega0 = None
         if wl["init"] == "noise":
             omega0 = [inputs.noise_omega0(wl["n"], wl["noise_amplitude"], wl["noise_seed"])]
-        cav = Cavity(Params(n=wl["n"], re=wl["re"], poisson_tol=wl["tol"], precision=prec),
+        cav = Cavity(Params(n=wl["n"], re=wl["re"], poisson_tol=wl["tol"], precision=prec,
+                            warm_start=args.warm_start),
                      device="cuda:0", stream=stream, omega0=omega0)
         if solver:
             cav.set_tuning(solver=solver)
@@ -316,6 +335,7 @@ def main():
     prec_override = None if args.precision is None else (
         CAVITY_MIXED if args.precision == "mixed" else CAVITY_FP64)
     cav, prec, head = single(args.workload, args.steps, args.warmup, args.exec,
+                             CAVITY_SOLVER_MG if args.solver == "multigrid" else 0,
                              precision=prec_override)
     wl = WORKLOADS[args.workload]
     n = wl["n"]
@@ -327,16 +347,22 @@ def main():
     cav.close()
 
     extras = {}
-    if not args.no_extras:
+    chosen = set() if args.no_extras else (
+        {"multigrid", "persistent", "resident", "re3e4", "n4096", "coupled", "re_sweep6_fp64",
+         "re_sweep6_mixed", "re_scan16_small_fp64"} if args.extras == "all"
+        else set(args.extras.split(",")))
+    if "multigrid" in chosen:
         # same workload, multigrid solver (same compact equation, same tolerance)
         cmg, _, mg = single(args.workload, args.steps, args.warmup, "stream", CAVITY_SOLVER_MG)
         mg["vcycles_per_stage"] = mg["sweeps_per_stage"] / 4 if mg["sweeps_per_stage"] else None
         cmg.close()
         extras["multigrid_1024_re1e4_fp64"] = mg
+    if "persistent" in chosen:
         # the persistent-kernel and resident-solve executions of the headline workload
         cp, _, pers = single(args.workload, args.extra_steps, 1, "persistent")
         cp.close()
         extras["persistent_1024_re1e4_fp64"] = pers
+    if "resident" in chosen:
         if args.exec != "resident":
             cr, _, res = single(args.workload, args.steps, args.warmup, "resident")
             cr.close()
@@ -345,6 +371,7 @@ def main():
             cs_, _, strm = single(args.workload, args.steps, args.warmup, "stream")
             cs_.close()
             extras["stream_1024_re1e4_fp64"] = strm
+    if "re3e4" in chosen:
         # FP64 and mixed + refinement on the same workload (1024^2, Re 3e4), with the
         # same steps and warm-up
         c64, _, r64 = single("cavity1024_re3e4_mixed", args.extra_steps, 1, args.exec,
@@ -357,15 +384,16 @@ def main():
         mixed["speedup_vs_fp64_same_workload"] = round(mixed["value"] / r64["value"], 3)
         cavm.close()
         extras["mixed_1024_re3e4"] = mixed
+    if "n4096" in chosen:
         # 4096^2, Re 3e4, noise start (the HBM-resident case): FP64 SOR and mixed SOR for
-        # the same first step, the rooflines of both sweep kernels at this size, and FP64
-        # multigrid
+        # the same steps (two after one warm-up), the rooflines of both sweep kernels at
+        # this size, and FP64 multigrid
         key4 = "cavity4096_re3e4_mixed_noise"
-        c4, _, f4 = single(key4, 1, 0, "stream", precision=CAVITY_FP64)
+        c4, _, f4 = single(key4, 2, 1, "stream", precision=CAVITY_FP64)
         f4["roofline_fp64_sweep"] = _sweep_roofline(torch, c4, stream, 40, 0, f"{key4}:fp64")
         c4.close()
         extras["cavity4096_re3e4_noise_fp64_sor"] = f4
-        c4, _, m4 = single(key4, 1, 0, "stream")
+        c4, _, m4 = single(key4, 2, 1, "stream")
         m4["roofline_fp32_sweep"] = _sweep_roofline(torch, c4, stream, 40, 1, f"{key4}:fp32")
         m4["speedup_vs_fp64_same_workload"] = round(m4["value"] / f4["value"], 3)
         c4.close()
@@ -380,6 +408,7 @@ def main():
         c4, _, g4 = single(key4, args.extra_steps, 1, "stream", CAVITY_SOLVER_MG, CAVITY_FP64)
         c4.close()
         extras["cavity4096_re3e4_noise_fp64_multigrid"] = g4
+    if "coupled" in chosen:
         # coupled mode: a fixed 20 sweeps per stage with beta = 0.8 (no stopping test)
         cc = Cavity(Params(n=n, re=wl["re"], fixed_sweeps=20, sor_omega=0.8), device="cuda:0",
                     stream=stream)
@@ -389,46 +418,48 @@ def main():
             "value": round(n * n * args.steps / el / 1e6, 4),
             "ms_per_step": round(1e3 * el / args.steps, 3),
             "sweeps_per_stage": st[0]["sweeps_last_step"] / 5, "steps": args.steps}
-        # batched Reynolds sweeps vs one cavity at a time: six cavities 256^2..1024^2
-        # (FP64 and mixed) and sixteen 128^2 cavities (FP64)
-        for wname, label, prec_b in (("re_sweep6", "fp64", CAVITY_FP64),
-                                     ("re_sweep6", "mixed", CAVITY_MIXED),
-                                     ("re_scan16_small", "fp64", CAVITY_FP64)):
-            b = WORKLOADS[wname]
-            cells = sum(m * m for _, m in b["members"])
-            cb = Cavity([Params(n=m, re=r, poisson_tol=b["tol"], precision=prec_b)
-                         for r, m in b["members"]], device="cuda:0", stream=stream)
-            default_exec = cb.exec_mode()
-            cb.set_exec(EXEC["graph"])
-            # the persistent kernel's tile shape chosen by the autotuner (timed rounds)
-            tuned = cb.autotune(-1, args.tune_cache)
-            el, _ = _timed_steps(torch, cb, args.extra_steps, 1)
-            cb.close()
-            # the same batch in stream execution: one stream per cavity
-            cb = Cavity([Params(n=m, re=r, poisson_tol=b["tol"], precision=prec_b)
-                         for r, m in b["members"]], device="cuda:0", stream=stream)
-            cb.set_exec(EXEC["stream"])
-            el_st, _ = _timed_steps(torch, cb, args.extra_steps, 1)
-            cb.close()
-            seq = 0.0
-            for r, m in b["members"]:
-                cs = Cavity(Params(n=m, re=r, poisson_tol=b["tol"], precision=prec_b),
-                            device="cuda:0", stream=stream)
-                e1, _ = _timed_steps(torch, cs, args.extra_steps, 1)
-                seq += e1
-                cs.close()
-            extras[f"{wname}_{label}"] = {
-                "cells": cells,
-                "batched_graph_mcell_steps_s": round(cells * args.extra_steps / el / 1e6, 4),
-                "batched_streams_mcell_steps_s": round(cells * args.extra_steps / el_st / 1e6, 4),
-                "sequential_stream_mcell_steps_s": round(cells * args.extra_steps / seq / 1e6, 4),
-                "speedup": round(seq / el, 3), "speedup_streams": round(seq / el_st, 3),
-                "default_exec": {v: k for k, v in EXEC.items()}[default_exec],
-                "graph_tuning": {k: tuned[k] for k in ("tile_x", "tile_y", "sweeps_per_launch",
-                                                       "threads", "tile_x32", "tile_y32",
-                                                       "sweeps_per_launch32", "threads32",
-                                                       "check_every", "inner_sweeps")},
-                "steps": args.extra_steps}
+    # batched Reynolds sweeps vs one cavity at a time: six cavities 256^2..1024^2
+    # (FP64 and mixed) and sixteen 128^2 cavities (FP64)
+    for wname, label, prec_b in (("re_sweep6", "fp64", CAVITY_FP64),
+                                 ("re_sweep6", "mixed", CAVITY_MIXED),
+                                 ("re_scan16_small", "fp64", CAVITY_FP64)):
+        if f"{wname}_{label}" not in chosen:
+            continue
+        b = WORKLOADS[wname]
+        cells = sum(m * m for _, m in b["members"])
+        cb = Cavity([Params(n=m, re=r, poisson_tol=b["tol"], precision=prec_b)
+                     for r, m in b["members"]], device="cuda:0", stream=stream)
+        default_exec = cb.exec_mode()
+        cb.set_exec(EXEC["graph"])
+        # the persistent kernel's tile shape chosen by the autotuner (timed rounds)
+        tuned = cb.autotune(-1, args.tune_cache)
+        el, _ = _timed_steps(torch, cb, args.extra_steps, 1)
+        cb.close()
+        # the same batch in stream execution: one stream per cavity
+        cb = Cavity([Params(n=m, re=r, poisson_tol=b["tol"], precision=prec_b)
+                     for r, m in b["members"]], device="cuda:0", stream=stream)
+        cb.set_exec(EXEC["stream"])
+        el_st, _ = _timed_steps(torch, cb, args.extra_steps, 1)
+        cb.close()
+        seq = 0.0
+        for r, m in b["members"]:
+            cs = Cavity(Params(n=m, re=r, poisson_tol=b["tol"], precision=prec_b),
+                        device="cuda:0", stream=stream)
+            e1, _ = _timed_steps(torch, cs, args.extra_steps, 1)
+            seq += e1
+            cs.close()
+        extras[f"{wname}_{label}"] = {
+            "cells": cells,
+            "batched_graph_mcell_steps_s": round(cells * args.extra_steps / el / 1e6, 4),
+            "batched_streams_mcell_steps_s": round(cells * args.extra_steps / el_st / 1e6, 4),
+            "sequential_stream_mcell_steps_s": round(cells * args.extra_steps / seq / 1e6, 4),
+            "speedup": round(seq / el, 3), "speedup_streams": round(seq / el_st, 3),
+            "default_exec": {v: k for k, v in EXEC.items()}[default_exec],
+            "graph_tuning": {k: tuned[k] for k in ("tile_x", "tile_y", "sweeps_per_launch",
+                                                   "threads", "tile_x32", "tile_y32",
+                                                   "sweeps_per_launch32", "threads32",
+                                                   "check_every", "inner_sweeps")},
+            "steps": args.extra_steps}
 
     cpu = None if args.no_cpu else _cpu_baseline(n, wl["re"], args.cpu_steps)
     line = {
@@ -437,9 +468,13 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == CAVITY_FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "re": wl["re"], "poisson_tol": wl["tol"],
-                   "precision": head["precision"], "init": wl["init"], "exec": head["exec"],
+                   "precision": head["precision"], "solver": head["solver"], "init": wl["init"],
+                   "exec": head["exec"],
                    "sweeps_per_stage": head["sweeps_per_stage"],
-                   "floor_limited_last_step": head["floor_limited_last_step"]},
+                   "floor_limited_last_step": head["floor_limited_last_step"],
+                   "warm_start_levels": args.warm_start or (
+                       CAVITY_WARM_LEVELS_MIXED if prec == CAVITY_MIXED
+                       else CAVITY_WARM_LEVELS_FP64)},
         "roofline": roofline,
         **({"roofline_fp32_sweep": head["roofline_fp32_sweep"]}
            if "roofline_fp32_sweep" in head else {}),

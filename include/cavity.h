@@ -61,6 +61,35 @@ enum cavity_precision {
                         stage accumulation of omega and FP64 wall vorticity    */
 };
 
+/* Starting value of the Poisson solve of each SSPRK stage (Sec. 3, eqs.
+ * SSPRK54_1-5 with eq. SequationFinal per stage).  The paper does not say
+ * what a solve starts from; a converged solve ends within poisson_tol of the
+ * same discrete solution from any start, so the choice changes the number of
+ * sweeps, not the result beyond that tolerance.  Values of
+ * cavity_params.warm_start:
+ *   0 (CAVITY_WARM_DEFAULT): for converged solves CAVITY_WARM_LEVELS_FP64
+ *     levels in FP64 and CAVITY_WARM_LEVELS_MIXED in mixed precision (the
+ *     fastest on the 1024^2 workloads: more levels leave the solves' own
+ *     tolerance-level differences, amplified by the extrapolation weights,
+ *     as the larger part of the start's error), CAVITY_WARM_PREVIOUS in the
+ *     coupled mode (fixed_sweeps > 0, whose fixed iteration starts from the
+ *     previous stage's psi by definition);
+ *   1 (CAVITY_WARM_PREVIOUS): the psi of the stage before;
+ *   2 ... 8 (levels): the polynomial through the same stage's solutions of
+ *     the last `levels` steps, evaluated at the current step.  Consecutive
+ *     steps' solutions of one stage differ by O(dt); the extrapolation error
+ *     is O(dt^levels).  Costs 5 * levels FP64 fields of workspace.  Right
+ *     after cavity_create (also with resume = 1) no step is on file: the
+ *     first steps use the steps on file, and the previous stage's psi while
+ *     fewer than two are. */
+enum cavity_warm_start {
+  CAVITY_WARM_DEFAULT = 0,
+  CAVITY_WARM_PREVIOUS = 1,
+  CAVITY_WARM_LEVELS_FP64 = 7,
+  CAVITY_WARM_LEVELS_MIXED = 6,
+  CAVITY_WARM_LEVELS_MAX = 8
+};
+
 /* Parameters of one cavity (Sec. 3.2: unit square, lid speed U on top). */
 typedef struct cavity_params {
   int32_t n;                  /* nodes per side including walls, 5 <= n <= 16385   */
@@ -77,7 +106,10 @@ typedef struct cavity_params {
   int32_t resume;             /* 1: omega0 and psi0 (both required) are a state
                                  saved by cavity_fields after a step and are
                                  adopted as they are, walls included, without a
-                                 Poisson solve, so the run continues exactly      */
+                                 Poisson solve, so the run continues exactly
+                                 with warm_start = CAVITY_WARM_PREVIOUS and
+                                 within the solve tolerance otherwise (the
+                                 extrapolation history starts empty)              */
   double sor_omega;           /* relaxation parameter in (0, 2); <= 0 chooses,
                                  for the coupled mode, w5 = 2 / (1 + sin(pi h)),
                                  and for converged solves w5 - 5/8 (w5 - w9),
@@ -102,7 +134,8 @@ typedef struct cavity_params {
                                  SOR solver and CAVITY_EXEC_STREAM; the initial
                                  solve of cavity_create and cavity_poisson still
                                  solve to poisson_tol                              */
-  int32_t reserved;           /* must be 0                                        */
+  int32_t warm_start;         /* enum cavity_warm_start: 0, 1 or 2 ... 8 levels;
+                                 0 or 1 when fixed_sweeps > 0                      */
 } cavity_params;
 
 /* Per-cavity results of cavity_step. */

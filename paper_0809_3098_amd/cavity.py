@@ -39,6 +39,11 @@ CAVITY_EXEC_GRAPH = 2
 CAVITY_EXEC_RESIDENT = 3
 CAVITY_SOLVER_SOR = 0
 CAVITY_SOLVER_MG = 1
+CAVITY_WARM_DEFAULT = 0
+CAVITY_WARM_PREVIOUS = 1
+CAVITY_WARM_LEVELS_FP64 = 7
+CAVITY_WARM_LEVELS_MIXED = 6
+CAVITY_WARM_LEVELS_MAX = 8
 
 _STATUS_NAMES = {0: "CAVITY_OK", -1: "CAVITY_EINVAL", -2: "CAVITY_ENOMEM", -3: "CAVITY_EHIP",
                  -4: "CAVITY_ENOCONV", -5: "CAVITY_ENONFINITE", -6: "CAVITY_ESTATE"}
@@ -60,7 +65,7 @@ class cavity_params(ctypes.Structure):
         ("poisson_max_sweeps", ctypes.c_int32), ("resume", ctypes.c_int32),
         ("sor_omega", ctypes.c_double),
         ("omega0", ctypes.c_void_p), ("psi0", ctypes.c_void_p),
-        ("fixed_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("fixed_sweeps", ctypes.c_int32), ("warm_start", ctypes.c_int32),
     ]
 
 
@@ -165,6 +170,7 @@ class Params:
     sor_omega: float = 0.0
     resume: int = 0
     fixed_sweeps: int = 0
+    warm_start: int = CAVITY_WARM_DEFAULT
 
     def to_c(self, omega0_ptr: int = 0, psi0_ptr: int = 0) -> cavity_params:
         return cavity_params(n=self.n, precision=self.precision, re=self.re, u_lid=self.u_lid,
@@ -172,7 +178,7 @@ class Params:
                              poisson_max_sweeps=self.poisson_max_sweeps, resume=self.resume,
                              sor_omega=self.sor_omega, omega0=omega0_ptr or None,
                              psi0=psi0_ptr or None, fixed_sweeps=self.fixed_sweeps,
-                             reserved=0)
+                             warm_start=self.warm_start)
 
 
 def _param_array(params: Sequence[cavity_params]):

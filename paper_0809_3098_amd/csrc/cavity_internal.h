@@ -252,6 +252,14 @@ hipError_t launch_copy(const double* src, double* dst, int n, int pitch, hipStre
 hipError_t launch_copy_interior(const double* src, double* dst, int n, int pitch,
                                 hipStream_t st);
 
+// Start of a stage's Poisson solve extrapolated from the same stage of the last
+// `levels` steps (2 <= levels <= 8), after filing the previous stage's psi in
+// the history (5 * levels pitched fields, fstride doubles apart); *count =
+// steps completed since the history was emptied, advanced by launch_warm_tick.
+hipError_t launch_warm(double* psi, double* hist, size_t fstride, int n, int pitch, int stage,
+                       int levels, const long long* count, hipStream_t st);
+hipError_t launch_warm_tick(long long* count, hipStream_t st);
+
 // Allocation-free Poisson solve: the largest grid it takes, the size of its
 // device scratch array, and that array's address on the current device
 // (looked up with hipGetSymbolAddress on the first call per device).

@@ -207,14 +207,15 @@ __device__ __forceinline__ T gs_target(T e, T sn, T ss, T dn, T ds, T f) {
   return fma_t(T(0.2), (q + lane_shift<kOther>(q)) + (sn + ss), f);
 }
 
-// The rows r_lo..r_hi of colour C in a thread's strip; xs / xd: the N / S
-// and diagonal neighbour values of the row beyond the strip (from LDS), used
-// by the row visited last.  (A second copy of the loop without the row tests,
-// for strips that lie inside the pass, doubled the vector instructions per
-// sweep: the compiler copied the register arrays between the two versions.)
+// The rows of colour C in a thread's strip that pass k updates (row r while
+// k <= ky[r]); xs / xd: the N / S and diagonal neighbour values of the row
+// beyond the strip (from LDS), used by the row visited last.  (A second copy
+// of the loop without the row tests, for strips that lie inside the pass,
+// doubled the vector instructions per sweep: the compiler copied the register
+// arrays between the two versions.)
 template <typename T, int K, int C>
 __device__ __forceinline__ void strip_rows(T (&pv)[4][K], const T (&fv)[4][K], T xs, T xd, T wl,
-                                           int r_lo, int r_hi) {
+                                           int k, const int (&ky)[K]) {
   constexpr int cx = C & 1, cy = C >> 1;
   constexpr int EW = cy * 2 + (1 - cx), NS = (1 - cy) * 2 + cx, DG = (1 - cy) * 2 + (1 - cx);
   if (cy == 0) {
@@ -225,7 +226,7 @@ __device__ __forceinline__ void strip_rows(T (&pv)[4][K], const T (&fv)[4][K], T
     for (int r = K - 1; r >= 0; --r) {
       const T sS = r > 0 ? pv[NS][r - 1] : xs;
       const T dS = r > 0 ? pv[DG][r - 1] : xd;
-      if (r >= r_lo && r <= r_hi) {  // wave-uniform
+      if (k <= ky[r]) {  // wave-uniform
         const T p = pv[C][r];
         pv[C][r] = fma_t(wl, gs_target<cx>(pv[EW][r], sN, sS, dN, dS, fv[C][r]) - p, p);
       }
@@ -240,7 +241,7 @@ __device__ __forceinline__ void strip_rows(T (&pv)[4][K], const T (&fv)[4][K], T
     for (int r = 0; r < K; ++r) {
       const T sN = r + 1 < K ? pv[NS][r + 1] : xs;
       const T dN = r + 1 < K ? pv[DG][r + 1] : xd;
-      if (r >= r_lo && r <= r_hi) {  // wave-uniform
+      if (k <= ky[r]) {  // wave-uniform
         const T p = pv[C][r];
         pv[C][r] = fma_t(wl, gs_target<cx>(pv[EW][r], sN, sS, dN, dS, fv[C][r]) - p, p);
       }
@@ -248,6 +249,42 @@ __device__ __forceinline__ void strip_rows(T (&pv)[4][K], const T (&fv)[4][K], T
       dS = dN;
     }
   }
+}
+
+// The last pass of a launch in which a node takes part.  Pass k (1 ... 4S)
+// updates the domain's interior nodes at least k nodes from the region's edge
+// (everything within distance k of such a node was loaded, so its value after
+// the pass is exact): a node at local (x, y) while k <= min(x, RX - 1 - x)
+// and k <= min(y, RY - 1 - y), a node outside the domain's interior never.
+// kx: per lane, for its x-parity 0 and 1 columns; ky: per plane row r of the
+// strip, for y-parity 0 and 1 (wave-uniform, scalar registers); kyall: the
+// last pass in which the strip has a row of that y-parity.  Computed once per
+// launch, they leave each pass one comparison per lane and per row.
+template <int K>
+struct PassLimits {
+  int kx[2];
+  int ky[2][K];
+  int kyall[2];
+};
+
+template <typename T, int TX, int TY, int S, int NT, int HX>
+__device__ __forceinline__ PassLimits<SorGeom<T, TX, TY, S, NT, HX>::K> pass_limits(
+    int lxd0, int lxd1, int lyd0, int lyd1, int lane, int b0) {
+  using G = SorGeom<T, TX, TY, S, NT, HX>;
+  PassLimits<G::K> lim;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int x = 2 * lane + c;
+    lim.kx[c] = (x >= lxd0 && x <= lxd1) ? min(x, G::RX - 1 - x) : -1;
+    lim.kyall[c] = -1;
+#pragma unroll
+    for (int r = 0; r < G::K; ++r) {
+      const int y = 2 * (b0 + r) + c;
+      lim.ky[c][r] = (y >= lyd0 && y <= lyd1) ? min(y, G::RY - 1 - y) : -1;
+      lim.kyall[c] = max(lim.kyall[c], lim.ky[c][r]);
+    }
+  }
+  return lim;
 }
 
 // One colour pass C (parity class (C & 1, C >> 1)) of pass number k over the
@@ -285,21 +322,15 @@ __device__ __forceinline__ void strip_rows(T (&pv)[4][K], const T (&fv)[4][K], T
 template <typename T, int TX, int TY, int S, int NT, int HX, int C>
 __device__ __forceinline__ void colour_pass(T* sp, T (&pv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
                                             const T (&fv)[4][SorGeom<T, TX, TY, S, NT, HX>::K],
-                                            int k, int lxd0, int lxd1, int lyd0, int lyd1,
+                                            int k,
+                                            const PassLimits<SorGeom<T, TX, TY, S, NT, HX>::K>& lim,
                                             int lane, int b0, T w, T xs, T xd) {
   using G = SorGeom<T, TX, TY, S, NT, HX>;
   constexpr int K = G::K;
   constexpr int cx = C & 1, cy = C >> 1;
-  constexpr int EW = cy * 2 + (1 - cx), NS = (1 - cy) * 2 + cx, DG = (1 - cy) * 2 + (1 - cx);
-  const int lxlo = max(k, lxd0), lxhi = min(G::RX - 1 - k, lxd1);
-  const int lylo = max(k, lyd0), lyhi = min(G::RY - 1 - k, lyd1);
-  const int a0 = (lxlo - cx + 1) >> 1, a1 = (lxhi - cx) >> 1;
-  // the strip's rows inside the pass (wave-uniform)
-  const int r_lo = max((lylo - cy + 1) >> 1, b0) - b0;
-  const int r_hi = min((lyhi - cy) >> 1, b0 + K - 1) - b0;
-  const T wl = (lane >= a0 && lane <= a1) ? w : T(0);
-  if (r_lo <= r_hi) {
-    strip_rows<T, K, C>(pv, fv, xs, xd, wl, r_lo, r_hi);
+  const T wl = (k <= lim.kx[cx]) ? w : T(0);
+  if (k <= lim.kyall[cy]) {  // wave-uniform
+    strip_rows<T, K, C>(pv, fv, xs, xd, wl, k, lim.ky[cy]);
     // publish the strip's boundary row of colour C (lanes beyond a plane row
     // store to the sink)
     constexpr int rp = cy == 0 ? 0 : K - 1;
@@ -609,19 +640,16 @@ __device__ __forceinline__ void tile_sweeps(T* pl, T (&pv)[4][SorGeom<T, TX, TY,
   const int ic = min(lane, G::RXH - 1);
   const T* below = pl + (b0 - 1) * G::RXH + ic;
   const T* above = pl + (b0 + G::K) * G::RXH + ic;
+  const PassLimits<G::K> lim = pass_limits<T, TX, TY, S, NT, HX>(lxd0, lxd1, lyd0, lyd1, lane, b0);
 #pragma unroll 1
   for (int s = 0; s < S; ++s) {
     const int k = 4 * s;
     const T l2 = below[2 * G::PLANE], l3 = below[3 * G::PLANE];
-    colour_pass<T, TX, TY, S, NT, HX, 0>(pl, pv, fv, k + 1, lxd0, lxd1, lyd0, lyd1, lane, b0, w,
-                                         l2, l3);
-    colour_pass<T, TX, TY, S, NT, HX, 1>(pl, pv, fv, k + 2, lxd0, lxd1, lyd0, lyd1, lane, b0, w,
-                                         l3, l2);
+    colour_pass<T, TX, TY, S, NT, HX, 0>(pl, pv, fv, k + 1, lim, lane, b0, w, l2, l3);
+    colour_pass<T, TX, TY, S, NT, HX, 1>(pl, pv, fv, k + 2, lim, lane, b0, w, l3, l2);
     const T u0 = above[0], u1 = above[G::PLANE];
-    colour_pass<T, TX, TY, S, NT, HX, 2>(pl, pv, fv, k + 3, lxd0, lxd1, lyd0, lyd1, lane, b0, w,
-                                         u0, u1);
-    colour_pass<T, TX, TY, S, NT, HX, 3>(pl, pv, fv, k + 4, lxd0, lxd1, lyd0, lyd1, lane, b0, w,
-                                         u1, u0);
+    colour_pass<T, TX, TY, S, NT, HX, 2>(pl, pv, fv, k + 3, lim, lane, b0, w, u0, u1);
+    colour_pass<T, TX, TY, S, NT, HX, 3>(pl, pv, fv, k + 4, lim, lane, b0, w, u1, u0);
   }
 }
 
@@ -1680,8 +1708,9 @@ __global__ void k_ctl_reset(PoissonCtl* c, double relax, double tol_hat, long lo
 
 // r = g(psi) - psi in FP64 on interior nodes, reduced to max |r| for the solve
 // decision; with R32 != nullptr also stored as float for the FP32 correction
-// solve, whose correction d32 then starts from zero.  Grid-stride over rows
-// with a bounded grid, so the partial-maximum array stays small.
+// solve, whose correction d32 then starts from zero.  Block b takes rows
+// 1 + b, 1 + b + gridDim.x, ... and its threads stride along each row (no
+// index division; a bounded grid keeps the partial-maximum array small).
 constexpr int kResidBlocks = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_resid64(const double* __restrict__ psi,
@@ -1692,24 +1721,21 @@ __global__ __launch_bounds__(kBlock) void k_resid64(const double* __restrict__ p
                                                     double* __restrict__ part) {
   if (ctl->state != SOLVE_RUN) return;
   double rmax = 0.0, pmax = 0.0;
-  const int m = n - 2;
-  const long long total = (long long)m * m;
-  for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < total;
-       t += (long long)gridDim.x * kBlock) {
-    const int j = 1 + (int)(t / m);
-    const int i = 1 + (int)(t - (long long)(j - 1) * m);
-    const size_t p = (size_t)j * pitch + i;
-    const double s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pitch] + psi[p - pitch]);
-    const double sd = (psi[p + pitch + 1] + psi[p + pitch - 1]) +
-                      (psi[p - pitch + 1] + psi[p - pitch - 1]);
-    const double g = fma(0.2, s4, fma(0.05, sd, F[p]));
-    const double r = g - psi[p];
-    if (R32) {
-      R32[p] = (float)r;
-      d32[p] = 0.0f;
+  for (int j = 1 + blockIdx.x; j <= n - 2; j += gridDim.x) {
+    for (int i = 1 + threadIdx.x; i <= n - 2; i += kBlock) {
+      const size_t p = (size_t)j * pitch + i;
+      const double s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pitch] + psi[p - pitch]);
+      const double sd = (psi[p + pitch + 1] + psi[p + pitch - 1]) +
+                        (psi[p - pitch + 1] + psi[p - pitch - 1]);
+      const double g = fma(0.2, s4, fma(0.05, sd, F[p]));
+      const double r = g - psi[p];
+      if (R32) {
+        R32[p] = (float)r;
+        d32[p] = 0.0f;
+      }
+      rmax = fmax(rmax, mag(r));
+      pmax = fmax(pmax, mag(psi[p]));
     }
-    rmax = fmax(rmax, mag(r));
-    pmax = fmax(pmax, mag(psi[p]));
   }
   // per-block maxima only; k_decide follows on the stream
   block_max2<kBlock>(rmax, pmax);
@@ -1748,20 +1774,19 @@ __global__ __launch_bounds__(kBlock) void k_diag_partial(const double* __restric
                                                          int pitch, double inv2h,
                                                          double* __restrict__ partial) {
   double s_psi = 0.0, s_w = 0.0, m_w = 0.0, s_ke = 0.0;
-  const long long total = (long long)n * n;
-  for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < total;
-       t += (long long)gridDim.x * kBlock) {
-    const int j = (int)(t / n);
-    const int i = (int)(t - (long long)j * n);
-    const size_t p = (size_t)j * pitch + i;
-    s_psi += fabs(psi1[p] - psi0[p]);
-    const double dw = fabs(w1[p] - w0[p]);
-    s_w += dw;
-    m_w = fmax(m_w, mag(dw));
-    if (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) {
-      const double u = (psi1[p + pitch] - psi1[p - pitch]) * inv2h;
-      const double v = -(psi1[p + 1] - psi1[p - 1]) * inv2h;
-      s_ke = fma(u, u, fma(v, v, s_ke));
+  // block b takes rows b, b + gridDim.x, ...; its threads stride along a row
+  for (int j = blockIdx.x; j < n; j += gridDim.x) {
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+      const size_t p = (size_t)j * pitch + i;
+      s_psi += fabs(psi1[p] - psi0[p]);
+      const double dw = fabs(w1[p] - w0[p]);
+      s_w += dw;
+      m_w = fmax(m_w, mag(dw));
+      if (i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2) {
+        const double u = (psi1[p + pitch] - psi1[p - pitch]) * inv2h;
+        const double v = -(psi1[p + 1] - psi1[p - 1]) * inv2h;
+        s_ke = fma(u, u, fma(v, v, s_ke));
+      }
     }
   }
   __shared__ double red[4][kBlock];
@@ -1876,6 +1901,53 @@ __global__ __launch_bounds__(kBlock) void k_copy(const double* __restrict__ src,
 }
 
 inline dim3 grid2d(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); }
+
+// Starting value of a stage's Poisson solve from the same stage's solutions of
+// the last `levels` steps.  hist holds `levels` slots per stage (stage k,
+// slot r at hist + ((k - 1) * levels + r) * fstride); step q's solution of
+// stage k sits in slot q mod levels.  *count is the number of steps completed
+// since the history was last emptied.  On entry psi holds the solution of the
+// stage before (stage 5 of the previous step when stage == 1): it is filed
+// first, then replaced, if at least two earlier steps of this stage are on
+// file, by the value at the current step of the polynomial through them
+// (extrapolation through L equally spaced points: weights (-1)^(q+1) C(L, q)
+// for the point q steps back).  The solve that follows converges to the same
+// tolerance from any start; a start whose error is O(dt^L) instead of O(dt)
+// saves the sweeps that would remove the difference.  Interior nodes only
+// (psi = 0 on walls in every slot).
+__global__ __launch_bounds__(kBlock) void k_warm(double* __restrict__ psi,
+                                                 double* __restrict__ hist, size_t fstride,
+                                                 int n, int pitch, int stage, int levels,
+                                                 const long long* __restrict__ count) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i < 1 || j < 1 || i >= n - 1 || j >= n - 1) return;
+  const long long s = *count;
+  const size_t p = (size_t)j * pitch + i;
+  const double cur = psi[p];
+  if (stage > 1)
+    hist[((size_t)(stage - 2) * levels + (int)(s % levels)) * fstride + p] = cur;
+  else if (s >= 1)
+    hist[((size_t)4 * levels + (int)((s - 1) % levels)) * fstride + p] = cur;
+  const int L = (int)(s < levels ? s : levels);
+  if (L < 2) return;
+  const double* hk = hist + (size_t)(stage - 1) * levels * fstride + p;
+  // oldest point first; binomial weights with alternating signs
+  double binom = 1.0, g = 0.0;
+  for (int q = L; q >= 1; --q) {
+    // C(L, q) from C(L, q + 1): * (q + 1) / (L - q), exact in doubles
+    if (q < L) binom = binom * (double)(q + 1) / (double)(L - q);
+    const double w = (q & 1) ? binom : -binom;
+    g = fma(w, hk[(size_t)((s - q) % levels) * fstride], g);
+  }
+  psi[p] = g;
+}
+
+// One more step is on file (after the step's last stage).
+__global__ void k_warm_tick(long long* count) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *count += 1;
+}
+
 
 // ---------------------------------------------------------------------------
 // Tile-configuration dispatch of the sweep kernels.
@@ -2113,8 +2185,7 @@ int resid_blocks() { return kResidBlocks; }
 hipError_t launch_resid64(const double* psi, const double* F, float* R32, float* d32, int n,
                           int pitch, PoissonCtl* ctl, double* part, hipStream_t st,
                           long long sweeps_done) {
-  const long long cells = (long long)(n - 2) * (n - 2);
-  const int blocks = (int)std::min<long long>(kResidBlocks, (cells + kBlock - 1) / kBlock);
+  const int blocks = std::min(kResidBlocks, n - 2);  // one interior row per block and pass
   hipLaunchKernelGGL(k_resid64, dim3(blocks), dim3(kBlock), 0, st, psi, F, R32, d32, n, pitch,
                      ctl, part);
   hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, st, ctl, part, blocks, sweeps_done);
@@ -2290,6 +2361,18 @@ hipError_t launch_copy(const double* src, double* dst, int n, int pitch, hipStre
 hipError_t launch_copy_interior(const double* src, double* dst, int n, int pitch,
                                 hipStream_t st) {
   hipLaunchKernelGGL(k_copy, grid2d(n, n), dim3(kBlock), 0, st, src, dst, n, pitch, 3);
+  return hipGetLastError();
+}
+
+hipError_t launch_warm(double* psi, double* hist, size_t fstride, int n, int pitch, int stage,
+                       int levels, const long long* count, hipStream_t st) {
+  hipLaunchKernelGGL(k_warm, grid2d(n, n), dim3(kBlock), 0, st, psi, hist, fstride, n, pitch,
+                     stage, levels, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_warm_tick(long long* count, hipStream_t st) {
+  hipLaunchKernelGGL(k_warm_tick, dim3(1), dim3(64), 0, st, count);
   return hipGetLastError();
 }
 

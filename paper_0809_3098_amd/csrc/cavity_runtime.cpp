@@ -113,6 +113,14 @@ struct Member {
   int inner_sweeps = 0;     // mixed: FP32 sweeps per refinement round
   int solver = CAVITY_SOLVER_SOR;
   int fixed = 0;            // > 0: sweeps per stage solve of the coupled mode
+  // Start of each stage's solve: 1 = the previous stage's psi; >= 2 = the
+  // extrapolation through that many steps' solutions of the same stage, kept
+  // in hist (5 * warm pitched fields, hist_stride doubles apart; stage k's
+  // slot r at (k - 1) * warm + r) with the count of steps on file in warm_cnt.
+  int warm = 1;
+  double* hist = nullptr;
+  size_t hist_stride = 0;
+  long long* warm_cnt = nullptr;
   std::vector<MgLevel> mg;  // multigrid hierarchy (allocated for every cavity)
   std::vector<MgLevel32> mg32;  // FP32 hierarchy (mixed cavities)
   // host-side state
@@ -217,7 +225,12 @@ int derive(const cavity_params& p, Member& m) {
     return fail(CAVITY_EINVAL, "resume = 1 needs both omega0 and psi0");
   if (p.precision != CAVITY_FP64 && p.precision != CAVITY_MIXED)
     return fail(CAVITY_EINVAL, "precision = %d is not CAVITY_FP64 or CAVITY_MIXED", p.precision);
-  if (p.reserved != 0) return fail(CAVITY_EINVAL, "reserved must be 0");
+  if (p.warm_start < 0 || p.warm_start > CAVITY_WARM_LEVELS_MAX)
+    return fail(CAVITY_EINVAL, "warm_start = %d outside [0, %d]", p.warm_start,
+                CAVITY_WARM_LEVELS_MAX);
+  if (p.fixed_sweeps > 0 && p.warm_start > CAVITY_WARM_PREVIOUS)
+    return fail(CAVITY_EINVAL, "warm_start extrapolation needs converged solves "
+                               "(fixed_sweeps = 0)");
   if (p.fixed_sweeps < 0 || p.fixed_sweeps > (1 << 24))
     return fail(CAVITY_EINVAL, "fixed_sweeps = %d outside [0, 2^24]", p.fixed_sweeps);
   if (p.fixed_sweeps > 0 && p.precision != CAVITY_FP64)
@@ -245,6 +258,10 @@ int derive(const cavity_params& p, Member& m) {
     m.dt = cfl * m.h / std::fabs(p.u_lid);
   }
   m.fixed = p.fixed_sweeps;
+  m.warm = p.warm_start != CAVITY_WARM_DEFAULT ? p.warm_start
+           : p.fixed_sweeps > 0              ? CAVITY_WARM_PREVIOUS
+           : p.precision == CAVITY_MIXED     ? CAVITY_WARM_LEVELS_MIXED
+                                             : CAVITY_WARM_LEVELS_FP64;
   m.tol = p.poisson_tol > 0 ? p.poisson_tol : 1e-10;
   m.max_sweeps = p.poisson_max_sweeps > 0 ? p.poisson_max_sweeps : 200LL * p.n;
   if (p.sor_omega > 0) {
@@ -354,6 +371,7 @@ size_t member_bytes(const Member& m) {
   b += align_up(4 * sizeof(double));
   b += mg_bytes(m.n);
   if (m.mixed) b += mg32_bytes(m.n);
+  if (m.warm >= 2) b += 5 * (size_t)m.warm * f64 + align_up(sizeof(long long));
   return b;
 }
 
@@ -383,6 +401,11 @@ void carve(Member& m, char*& cur) {
   m.diag_np = cav::diag_partials(m.n);
   m.diag_partial = reinterpret_cast<double*>(take(align_up((size_t)m.diag_np * 4 * 8)));
   m.diag_out = reinterpret_cast<double*>(take(align_up(4 * sizeof(double))));
+  if (m.warm >= 2) {
+    m.hist_stride = f64 / sizeof(double);
+    m.hist = reinterpret_cast<double*>(take(5 * (size_t)m.warm * f64));
+    m.warm_cnt = reinterpret_cast<long long*>(take(align_up(sizeof(long long))));
+  }
   const std::vector<int> v = mg_sizes(m.n);
   m.mg.assign(v.size(), MgLevel{});
   for (size_t l = 0; l < v.size(); ++l) {
@@ -975,7 +998,14 @@ int enqueue_stage_one(cavity_s* h, Member& m, int stage) {
     }
     HIP_TRY(h, cav::launch_stage(m.psi, m.mixed ? m.psi32 : nullptr, w0, win, wx, out, wp, pout,
                                  m.n, m.pitch, a, h->st));
-    return enqueue_rhs_and_walls_prep(h, m, out);
+    const int rc = enqueue_rhs_and_walls_prep(h, m, out);
+    if (rc != CAVITY_OK) return rc;
+    // the stage's transport has read psi: file it and start the solve from
+    // the extrapolation
+    if (m.warm >= 2)
+      HIP_TRY(h, cav::launch_warm(m.psi, m.hist, m.hist_stride, m.n, m.pitch, stage, m.warm,
+                                  m.warm_cnt, h->st));
+    return CAVITY_OK;
   }
 }
 
@@ -994,6 +1024,10 @@ int enqueue_thom(cavity_s* h, int stage) {
     Member& m = h->m[k];
     HIP_TRY(h, cav::launch_thom(m.psi, stage_output(m, stage), m.n, m.pitch, m.h, m.u_lid,
                                 member_stream(h, k)));
+    // the step's five solutions are (or, for the last stage's, will be at the
+    // next step's first stage) on file
+    if (stage == 5 && m.warm >= 2)
+      HIP_TRY(h, cav::launch_warm_tick(m.warm_cnt, member_stream(h, k)));
   }
   return CAVITY_OK;
 }
@@ -1453,6 +1487,9 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
     return bail(fail(CAVITY_EHIP, "zero fill failed"));
   for (Member& m : h->m) {
     if (cav::launch_zero(m.ctl, sizeof(cav::PoissonCtl), h->st) != hipSuccess)
+      return bail(fail(CAVITY_EHIP, "zero fill failed"));
+    // no step on file yet
+    if (m.warm_cnt && cav::launch_zero(m.warm_cnt, sizeof(long long), h->st) != hipSuccess)
       return bail(fail(CAVITY_EHIP, "zero fill failed"));
     for (int k = 0; k < 4; ++k)
       if (cav::launch_fill(m.w[k], m.n, m.pitch, 0.0, h->st) != hipSuccess)

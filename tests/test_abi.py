@@ -85,11 +85,33 @@ def test_workspace_bytes_scales_with_grid(binding):
     assert big > 20 * small
     # eight FP64 fields of 1024 x 1024 at least
     assert big >= 8 * 1024 * 1024 * 8
-    mixed = binding.cavity_workspace_bytes([P(n=1024, precision=binding.CAVITY_MIXED).to_c()])
-    assert mixed >= big + 3 * 1024 * 1024 * 4
+    # (without the warm-start history, whose default depth depends on precision)
+    fp64 = binding.cavity_workspace_bytes([P(n=1024, warm_start=1).to_c()])
+    mixed = binding.cavity_workspace_bytes([P(n=1024, precision=binding.CAVITY_MIXED,
+                                              warm_start=1).to_c()])
+    assert mixed >= fp64 + 3 * 1024 * 1024 * 4
     two = binding.cavity_workspace_bytes([P(n=64).to_c(), P(n=1024).to_c()])
     # one shared handle area (descriptors, barrier flags) instead of two
     assert small + big - 600 * 1024 <= two < small + big
+
+
+def test_workspace_bytes_holds_the_warm_start_history(binding):
+    """Extrapolated warm starts keep 5 fields (one per SSPRK stage) per level."""
+    P = binding.Params
+    field = 1024 * 1024 * 8   # 1024 nodes a side, pitch 1024
+    prev = binding.cavity_workspace_bytes([P(n=1024, warm_start=1).to_c()])
+    for levels in range(2, binding.CAVITY_WARM_LEVELS_MAX + 1):
+        got = binding.cavity_workspace_bytes([P(n=1024, warm_start=levels).to_c()])
+        assert got - prev == 5 * levels * field + 256
+    default = binding.cavity_workspace_bytes([P(n=1024).to_c()])
+    assert default - prev == 5 * binding.CAVITY_WARM_LEVELS_FP64 * field + 256
+    mixed_prev = binding.cavity_workspace_bytes(
+        [P(n=1024, precision=binding.CAVITY_MIXED, warm_start=1).to_c()])
+    mixed = binding.cavity_workspace_bytes([P(n=1024, precision=binding.CAVITY_MIXED).to_c()])
+    assert mixed - mixed_prev == 5 * binding.CAVITY_WARM_LEVELS_MIXED * field + 256
+    # the coupled mode starts every stage from the previous stage's psi
+    fixed = binding.cavity_workspace_bytes([P(n=1024, fixed_sweeps=8).to_c()])
+    assert fixed == prev
 
 
 @pytest.mark.parametrize("kw,msg", [
@@ -102,6 +124,9 @@ def test_workspace_bytes_scales_with_grid(binding):
     (dict(n=64, resume=1), "resume"),
     (dict(n=64, fixed_sweeps=-1), "fixed_sweeps"),
     (dict(n=64, fixed_sweeps=4, precision=1), "fixed_sweeps needs"),
+    (dict(n=64, warm_start=9), "warm_start"),
+    (dict(n=64, warm_start=-1), "warm_start"),
+    (dict(n=64, fixed_sweeps=4, warm_start=2), "warm_start extrapolation"),
 ])
 def test_invalid_parameters_are_rejected(binding, kw, msg):
     with pytest.raises(binding.CavityError) as e:

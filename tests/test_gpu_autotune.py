@@ -51,7 +51,10 @@ def test_autotune_mixed_and_batch(cm, tmp_path, precision):
     members = [(5000.0, 128), (10000.0, 256)]
     cache = str(tmp_path / "tune.jsonl")
     print(f"[autotune batch] precision={precision}", flush=True)
-    c = cm.Cavity([cm.Params(n=n, re=re, precision=precision) for re, n in members])
+    # FP64: solves to 1e-11 (see the note on few-step runs in test_gpu_batch)
+    tol = 1e-11 if precision == 0 else 1e-10
+    c = cm.Cavity([cm.Params(n=n, re=re, precision=precision, poisson_tol=tol)
+                   for re, n in members])
     c.step(1, want_stats=False)
     c.autotune(0, cache)
     c.autotune(1, cache)
@@ -67,6 +70,7 @@ def test_autotune_mixed_and_batch(cm, tmp_path, precision):
         ref = CavityOracle(128, 5000.0)
         ref.step(4)
         ep, ew = rel(psi, ref.psi), rel(omega, ref.omega)
+        print(f"  psi {ep:.3e} omega {ew:.3e}")
         assert ep <= 1e-11 and ew <= 1e-11, (ep, ew)
     else:
         # the precision design's tolerances (see test_gpu_mixed), which reject

@@ -68,11 +68,20 @@ def test_batch_bitwise_equals_solo_runs(cm, mode, precision):
 
 
 def test_reynolds_sweep_six_cavities_graph(cm):
-    """The six-cavity Reynolds sweep (256^2 ... 1024^2) in graph mode."""
+    """The six-cavity Reynolds sweep (256^2 ... 1024^2) in graph mode, every
+    member against the oracle at 1e-11.
+
+    A few steps from rest psi is still small (max |psi| of order 1e-3), and a
+    solve that stops as soon as its residual is below the tolerance t leaves
+    an error up to ||A^-1|| t = 0.074 t in psi: relative to max |psi| that is
+    above 1e-11 for t = 1e-10 (the error of the extrapolated starts often
+    sits near it, since their solves stop at the first check below t).  The
+    run solves to 1e-11, where the bar checks the execution mode rather than
+    the tolerance."""
     members = SWEEP6
     steps = 3
     print("[re sweep] six cavities", flush=True)
-    c = cm.Cavity([cm.Params(n=n, re=re) for re, n in members])
+    c = cm.Cavity([cm.Params(n=n, re=re, poisson_tol=1e-11) for re, n in members])
     # cavities this large default to a stream each; the graph is still there
     assert c.exec_mode() == cm.CAVITY_EXEC_STREAM
     c.set_exec(cm.CAVITY_EXEC_GRAPH)

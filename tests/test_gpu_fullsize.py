@@ -88,7 +88,10 @@ def test_largest_grid_sampled_sweeps(cm):
     n, relax = 16385, 1.7
     print(f"[largest grid] n={n}", flush=True)
     omega = inputs.random_field(n, seed=5)
-    c = cm.Cavity(cm.Params(n=n, re=1000.0, sor_omega=relax, poisson_max_sweeps=12))
+    # no extrapolation history (5 * levels fields of 2 GiB each at this size):
+    # the test takes no time step
+    c = cm.Cavity(cm.Params(n=n, re=1000.0, sor_omega=relax, poisson_max_sweeps=12,
+                            warm_start=cm.CAVITY_WARM_PREVIOUS))
     c.set_tuning(check_every=2 * c.tuning()["sweeps_per_launch"])
     psi, info = c.poisson(0, omega, allow_noconv=True)
     c.close()

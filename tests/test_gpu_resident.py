@@ -97,7 +97,10 @@ def test_resident_steps_match_oracle_and_stream(cm, n, re, steps):
 def test_resident_mode_runs_other_cavities_as_stream(cm):
     print("[resident fallback]", flush=True)
     n, steps = 130, 5
-    members = [cm.Params(n=n, re=2000.0), cm.Params(n=n, re=2.0e4, precision=cm.CAVITY_MIXED)]
+    # the FP64 cavity solves to 1e-11 for the 1e-11 bar after a few steps from
+    # rest (see the six-cavity test in test_gpu_batch)
+    members = [cm.Params(n=n, re=2000.0, poisson_tol=1e-11),
+               cm.Params(n=n, re=2.0e4, precision=cm.CAVITY_MIXED)]
     c = cm.Cavity(members)
     c.set_exec(cm.CAVITY_EXEC_RESIDENT)
     assert c.exec_mode() == cm.CAVITY_EXEC_RESIDENT

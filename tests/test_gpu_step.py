@@ -4,8 +4,9 @@ All calls go through the C ABI.  Tolerance: 1e-11 relative max-norm in psi
 and omega (the FP64 path), for the 64 x 64, Re = 1000 cavity over 200 steps
 and the 1024 x 1024, Re = 1e4 cavity after 100 steps, plus ragged sizes.
 Also: psi walls stay exactly zero, runs are bitwise repeatable, mirror
-symmetry, exact power-of-two velocity scaling, bitwise resume, the monitors,
-batching, and the error paths.
+symmetry, exact power-of-two velocity scaling, resume (bitwise when each
+solve starts from the previous stage's psi), the extrapolated warm starts, the
+monitors, batching, and the error paths.
 """
 import numpy as np
 import pytest
@@ -114,19 +115,68 @@ def test_power_of_two_scaling_is_exact(cm):
     assert np.array_equal(pb, 2.0 * pa) and np.array_equal(wb, 2.0 * wa)
 
 
-def test_resume_is_bitwise(cm):
-    n, re = 96, 1500.0
-    print(f"[resume] n={n}", flush=True)
-    (p20, w20, _, _), _ = _run_gpu(cm, n, re, 20)
-    a = cm.Cavity(cm.Params(n=n, re=re))
-    a.step(10, want_stats=False)
+def _resumed(cm, n, re, first, then, **kw):
+    a = cm.Cavity(cm.Params(n=n, re=re, **kw))
+    a.step(first, want_stats=False)
     p10, w10, _, _ = a.fields()
     a.close()
-    b = cm.Cavity(cm.Params(n=n, re=re, resume=1), omega0=[w10], psi0=[p10])
-    b.step(10, want_stats=False)
+    b = cm.Cavity(cm.Params(n=n, re=re, resume=1, **kw), omega0=[w10], psi0=[p10])
+    b.step(then, want_stats=False)
     p, w, _, _ = b.fields()
     b.close()
+    return p, w
+
+
+def test_resume_is_bitwise(cm):
+    """Each stage's solve starting from the previous stage's psi: the saved
+    state is all there is, and the resumed run repeats the uninterrupted one."""
+    n, re = 96, 1500.0
+    print(f"[resume] n={n}", flush=True)
+    prev = cm.CAVITY_WARM_PREVIOUS
+    (p20, w20, _, _), _ = _run_gpu(cm, n, re, 20, warm_start=prev)
+    p, w = _resumed(cm, n, re, 10, 10, warm_start=prev)
     assert np.array_equal(p, p20) and np.array_equal(w, w20)
+
+
+def test_resume_with_extrapolated_starts(cm):
+    """The default extrapolated starts: the resumed run starts a new history,
+    so its solves start elsewhere and end elsewhere within the tolerance; both
+    runs stay at FP64 parity with the oracle."""
+    n, re = 96, 1500.0
+    print(f"[resume extrapolated] n={n}", flush=True)
+    (p20, w20, _, _), _ = _run_gpu(cm, n, re, 20)
+    p, w = _resumed(cm, n, re, 10, 10)
+    ref = CavityOracle(n, re)
+    ref.step(20)
+    for a, b in ((p20, ref.psi), (w20, ref.omega), (p, ref.psi), (w, ref.omega)):
+        assert _rel(a, b) <= PARITY
+
+
+@pytest.mark.parametrize("n,re,steps", [(257, 1.0e4, 24), (1024, 1.0e4, 12)])
+def test_extrapolated_starts_save_sweeps_at_parity(cm, n, re, steps):
+    """Every warm start reaches the same FP64 parity with the oracle; the
+    extrapolation through more steps needs fewer sweeps (Sec. 3: each stage
+    solves eq. SequationFinal to the tolerance from whatever start)."""
+    print(f"[warm start] n={n} re={re} steps={steps}", flush=True)
+    ref = CavityOracle(n, re, workers=-1)
+    ref.step(steps)
+    sweeps = {}
+    for levels in range(1, cm.CAVITY_WARM_LEVELS_MAX + 1):
+        (psi, omega, _, _), st = _run_gpu(cm, n, re, steps, warm_start=levels)
+        ep, ew = _rel(psi, ref.psi), _rel(omega, ref.omega)
+        sweeps[levels] = st["sweeps_last_step"]
+        print(f"  levels={levels} psi_rel={ep:.3e} omega_rel={ew:.3e} "
+              f"sweeps/step={sweeps[levels]}")
+        assert st["status"] == 0
+        assert ep <= PARITY and ew <= PARITY, (levels, ep, ew)
+    # each further step on file removes sweeps (measured, levels 1 ... 8: 19360
+    # ... 10450 sweeps per step at 1024^2 after 12 steps, 4560 ... 1350 at
+    # 257^2 after 24)
+    for levels in range(2, cm.CAVITY_WARM_LEVELS_MAX + 1):
+        assert sweeps[levels] < sweeps[levels - 1], sweeps
+    assert sweeps[cm.CAVITY_WARM_LEVELS_FP64] <= 0.7 * sweeps[1]
+    (_, _, _, _), st = _run_gpu(cm, n, re, steps)
+    assert st["sweeps_last_step"] == sweeps[cm.CAVITY_WARM_LEVELS_FP64]
 
 
 def test_batch_streams_equal_sequential(cm):
