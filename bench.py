@@ -8,14 +8,17 @@ A step is one SSPRK(5,4) step of the whole hot path (five stages, each with
 transport RHS + stage combination, compact-Poisson SOR solve to tolerance,
 Thom walls).  The headline workload is the 1024 x 1024 cavity at Re = 1e4,
 started from rest, FP64, Poisson tolerance 1e-10, solved by the paper's
-relaxation (four-colour SOR).  Inputs are resident in HBM when timing starts.
-Extras (same JSON line): the same workload with the multigrid solver and in
-persistent execution; the 1024 x 1024 Re = 3e4 cavity in FP64 and in mixed
-precision (same steps); the 4096 x 4096 Re = 3e4 noise-start cavity (FP64 SOR
-and mixed SOR for the same two steps after one warm-up step, with the rooflines of both sweep kernels at
-that size, and FP64 multigrid); the six-cavity Reynolds sweep (256^2 ...
-1024^2) batched in one persistent launch per stage (hipGraph, tile shape from
-the autotuner) vs the same cavities run one by one.  Prints one JSON line.
+relaxation (four-colour SOR), timed over 1000 steps (the workload's run
+length) after 5 warm-up steps.  Inputs are resident in HBM when timing starts.
+Extras (same JSON line): the same workload with the multigrid solver, in
+persistent execution and with resident solves; the 1024 x 1024 Re = 3e4
+cavity in FP64 and in mixed precision (the same 200 steps); the 4096 x 4096
+Re = 3e4 noise-start cavity (FP64 SOR and mixed SOR for the same two steps
+after one warm-up step, with the rooflines of both sweep kernels at that size,
+and FP64 multigrid); the coupled mode; the six-cavity Reynolds sweep (256^2
+... 1024^2) and sixteen 128^2 cavities batched in one persistent launch per
+stage (hipGraph, tile shape from the autotuner) against a stream per cavity
+and the same cavities run one by one.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -150,7 +153,8 @@ def _sweep_roofline(torch, cav, stream, launches, arith, key):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
+    # the headline workload's whole run (1000 steps from rest), after 5 warm-up steps
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cavity1024_re1e4_fp64")
     ap.add_argument("--exec", default="stream", choices=sorted(EXEC))
@@ -167,12 +171,18 @@ def main():
                          "re_scan16_small_fp64 (default all)")
     ap.add_argument("--solver", default="sor", choices=["sor", "multigrid"],
                     help="Poisson solver of the headline workload")
+    ap.add_argument("--set-tuning", default="", metavar="KEY=VALUE,...",
+                    help="launch configuration of the headline cavity (cavity_set_tuning "
+                         "fields, e.g. check_every=64,inner_sweeps=300)")
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--relax-launches", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a cold 1 GiB device copy (torch), the known-size kernel the "
                          "HBM counters of a profiling run are scaled by")
     ap.add_argument("--extra-steps", type=int, default=10)
+    ap.add_argument("--compare-steps", type=int, default=200,
+                    help="steps of the FP64 and mixed runs of the 1024^2 Re 3e4 workload "
+                         "(after --warmup steps)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON-lines cache of the autotuner (default: none, tune every run)")
     ap.add_argument("--log-run", default=None, metavar="JSONL",
@@ -305,7 +315,7 @@ def main():
                 cav.close()
         return
 
-    def single(name, steps, warmup, mode, solver=0, precision=None):
+    def single(name, steps, warmup, mode, solver=0, precision=None, tuning=None):
         wl = WORKLOADS[name]
         prec = CAVITY_MIXED if wl["precision"] == "mixed" else CAVITY_FP64
         if precision is not None:
@@ -318,6 +328,8 @@ def main():
                      device="cuda:0", stream=stream, omega0=omega0)
         if solver:
             cav.set_tuning(solver=solver)
+        if tuning:
+            cav.set_tuning(**tuning)
         cav.set_exec(EXEC[mode])
         el, stats = _timed_steps(torch, cav, steps, warmup)
         n = wl["n"]
@@ -334,9 +346,13 @@ def main():
     # ---- headline: FP64 1024^2
     prec_override = None if args.precision is None else (
         CAVITY_MIXED if args.precision == "mixed" else CAVITY_FP64)
+    head_tuning = {}
+    for kv in filter(None, args.set_tuning.split(",")):
+        key, val = kv.split("=")
+        head_tuning[key] = float(val) if key == "sor_omega" else int(val)
     cav, prec, head = single(args.workload, args.steps, args.warmup, args.exec,
                              CAVITY_SOLVER_MG if args.solver == "multigrid" else 0,
-                             precision=prec_override)
+                             precision=prec_override, tuning=head_tuning)
     wl = WORKLOADS[args.workload]
     n = wl["n"]
     roofline = _sweep_roofline(torch, cav, stream, args.relax_launches, 0,
@@ -374,11 +390,12 @@ def main():
     if "re3e4" in chosen:
         # FP64 and mixed + refinement on the same workload (1024^2, Re 3e4), with the
         # same steps and warm-up
-        c64, _, r64 = single("cavity1024_re3e4_mixed", args.extra_steps, 1, args.exec,
-                             precision=CAVITY_FP64)
+        c64, _, r64 = single("cavity1024_re3e4_mixed", args.compare_steps, args.warmup,
+                             args.exec, precision=CAVITY_FP64)
         c64.close()
         extras["sor_fp64_1024_re3e4"] = r64
-        cavm, _, mixed = single("cavity1024_re3e4_mixed", args.extra_steps, 1, args.exec)
+        cavm, _, mixed = single("cavity1024_re3e4_mixed", args.compare_steps, args.warmup,
+                                args.exec)
         mixed["roofline_fp32_sweep"] = _sweep_roofline(torch, cavm, stream, args.relax_launches,
                                                        1, "cavity1024_re3e4_mixed:fp32")
         mixed["speedup_vs_fp64_same_workload"] = round(mixed["value"] / r64["value"], 3)
@@ -472,6 +489,7 @@ def main():
                    "exec": head["exec"],
                    "sweeps_per_stage": head["sweeps_per_stage"],
                    "floor_limited_last_step": head["floor_limited_last_step"],
+                   **({"tuning": head_tuning} if head_tuning else {}),
                    "warm_start_levels": args.warm_start or (
                        CAVITY_WARM_LEVELS_MIXED if prec == CAVITY_MIXED
                        else CAVITY_WARM_LEVELS_FP64)},

@@ -310,6 +310,15 @@ typedef struct cavity_tuning {
   int32_t xcd_bands;             /* 1: each XCD relaxes a contiguous band of tiles */
   int32_t solver;                /* enum cavity_solver                              */
   double sor_omega;              /* relaxation parameter in (0, 2)                 */
+  int32_t warm_degree;           /* extrapolated warm starts (warm_start = L >= 2
+                                    levels): degree d of the polynomial through the
+                                    L steps on file, 1 <= d <= L - 1; d = L - 1
+                                    interpolates them, a lower degree is their
+                                    least-squares fit, which passes on less of the
+                                    solves' own tolerance-level differences.  0 in
+                                    cavity_set_tuning keeps the current degree;
+                                    cavity_get_tuning reports 0 when the cavity
+                                    has no extrapolated starts                      */
 } cavity_tuning;
 
 /*

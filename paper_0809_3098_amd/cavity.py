@@ -99,7 +99,7 @@ class cavity_tuning(ctypes.Structure):
         ("sweeps_per_launch32", ctypes.c_int32), ("threads32", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("inner_sweeps", ctypes.c_int32),
         ("xcd_bands", ctypes.c_int32), ("solver", ctypes.c_int32),
-        ("sor_omega", ctypes.c_double),
+        ("sor_omega", ctypes.c_double), ("warm_degree", ctypes.c_int32),
     ]
 
     def as_dict(self):

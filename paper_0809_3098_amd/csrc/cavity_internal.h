@@ -107,7 +107,7 @@ size_t resident_flag_bytes(int n);
 // Upper bound on the blocks of any sweep launch (smallest tile) and of the
 // residual kernel: sizes the partial-maximum array.
 int sor_max_blocks(int n);
-int resid_blocks();
+int resid_blocks(int n);
 
 // ---- launches (all enqueue on `st`, return hipError_t) --------------------
 
@@ -256,8 +256,10 @@ hipError_t launch_copy_interior(const double* src, double* dst, int n, int pitch
 // `levels` steps (2 <= levels <= 8), after filing the previous stage's psi in
 // the history (5 * levels pitched fields, fstride doubles apart); *count =
 // steps completed since the history was emptied, advanced by launch_warm_tick.
+// wtab: device table, row L (kWarmCols doubles) = the weights for L steps on file.
+constexpr int kWarmCols = 8;
 hipError_t launch_warm(double* psi, double* hist, size_t fstride, int n, int pitch, int stage,
-                       int levels, const long long* count, hipStream_t st);
+                       int levels, const long long* count, const double* wtab, hipStream_t st);
 hipError_t launch_warm_tick(long long* count, hipStream_t st);
 
 // Allocation-free Poisson solve: the largest grid it takes, the size of its

@@ -1708,10 +1708,15 @@ __global__ void k_ctl_reset(PoissonCtl* c, double relax, double tol_hat, long lo
 
 // r = g(psi) - psi in FP64 on interior nodes, reduced to max |r| for the solve
 // decision; with R32 != nullptr also stored as float for the FP32 correction
-// solve, whose correction d32 then starts from zero.  Block b takes rows
-// 1 + b, 1 + b + gridDim.x, ... and its threads stride along each row (no
-// index division; a bounded grid keeps the partial-maximum array small).
-constexpr int kResidBlocks = 1024;
+// solve, whose correction d32 then starts from zero.  A block of 256 threads
+// takes a tile of 64 x 16 interior nodes, each thread four rows of one column
+// with all loads issued together; its two maxima go to the partial array
+// (one pair per block), which k_decide reduces.
+constexpr int kResidTileX = 64, kResidTileY = 16;
+
+inline dim3 resid_grid(int n) {
+  return dim3((n - 2 + kResidTileX - 1) / kResidTileX, (n - 2 + kResidTileY - 1) / kResidTileY);
+}
 
 __global__ __launch_bounds__(kBlock) void k_resid64(const double* __restrict__ psi,
                                                     const double* __restrict__ F,
@@ -1721,27 +1726,31 @@ __global__ __launch_bounds__(kBlock) void k_resid64(const double* __restrict__ p
                                                     double* __restrict__ part) {
   if (ctl->state != SOLVE_RUN) return;
   double rmax = 0.0, pmax = 0.0;
-  for (int j = 1 + blockIdx.x; j <= n - 2; j += gridDim.x) {
-    for (int i = 1 + threadIdx.x; i <= n - 2; i += kBlock) {
-      const size_t p = (size_t)j * pitch + i;
-      const double s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pitch] + psi[p - pitch]);
-      const double sd = (psi[p + pitch + 1] + psi[p + pitch - 1]) +
-                        (psi[p - pitch + 1] + psi[p - pitch - 1]);
-      const double g = fma(0.2, s4, fma(0.05, sd, F[p]));
-      const double r = g - psi[p];
-      if (R32) {
-        R32[p] = (float)r;
-        d32[p] = 0.0f;
-      }
-      rmax = fmax(rmax, mag(r));
-      pmax = fmax(pmax, mag(psi[p]));
+  const int i = 1 + blockIdx.x * kResidTileX + (threadIdx.x & 63);
+  const int jb = 1 + blockIdx.y * kResidTileY + (threadIdx.x >> 6);
+#pragma unroll
+  for (int q = 0; q < kResidTileY / 4; ++q) {
+    const int j = jb + 4 * q;
+    if (i > n - 2 || j > n - 2) continue;
+    const size_t p = (size_t)j * pitch + i;
+    const double s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pitch] + psi[p - pitch]);
+    const double sd = (psi[p + pitch + 1] + psi[p + pitch - 1]) +
+                      (psi[p - pitch + 1] + psi[p - pitch - 1]);
+    const double g = fma(0.2, s4, fma(0.05, sd, F[p]));
+    const double r = g - psi[p];
+    if (R32) {
+      R32[p] = (float)r;
+      d32[p] = 0.0f;
     }
+    rmax = fmax(rmax, mag(r));
+    pmax = fmax(pmax, mag(psi[p]));
   }
   // per-block maxima only; k_decide follows on the stream
   block_max2<kBlock>(rmax, pmax);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = rmax;
-    part[2 * blockIdx.x + 1] = pmax;
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    part[2 * b] = rmax;
+    part[2 * b + 1] = pmax;
   }
 }
 
@@ -1909,16 +1918,19 @@ inline dim3 grid2d(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); 
 // since the history was last emptied.  On entry psi holds the solution of the
 // stage before (stage 5 of the previous step when stage == 1): it is filed
 // first, then replaced, if at least two earlier steps of this stage are on
-// file, by the value at the current step of the polynomial through them
-// (extrapolation through L equally spaced points: weights (-1)^(q+1) C(L, q)
-// for the point q steps back).  The solve that follows converges to the same
-// tolerance from any start; a start whose error is O(dt^L) instead of O(dt)
-// saves the sweeps that would remove the difference.  Interior nodes only
-// (psi = 0 on walls in every slot).
+// file, by the value at the current step of the polynomial through them:
+// sum over q of w_q times the solution q steps back, with the weights of row
+// L = min(steps on file, levels) of wtab (kWarmCols doubles per row; for the
+// interpolating polynomial w_q = (-1)^(q+1) C(L, q)).  The solve that follows
+// converges to the same tolerance from any start; a start whose error is
+// O(dt^L) instead of O(dt) saves the sweeps that would remove the difference.
+// Interior nodes only (psi = 0 on walls in every slot).
+
 __global__ __launch_bounds__(kBlock) void k_warm(double* __restrict__ psi,
                                                  double* __restrict__ hist, size_t fstride,
                                                  int n, int pitch, int stage, int levels,
-                                                 const long long* __restrict__ count) {
+                                                 const long long* __restrict__ count,
+                                                 const double* __restrict__ wtab) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i < 1 || j < 1 || i >= n - 1 || j >= n - 1) return;
@@ -1932,14 +1944,10 @@ __global__ __launch_bounds__(kBlock) void k_warm(double* __restrict__ psi,
   const int L = (int)(s < levels ? s : levels);
   if (L < 2) return;
   const double* hk = hist + (size_t)(stage - 1) * levels * fstride + p;
-  // oldest point first; binomial weights with alternating signs
-  double binom = 1.0, g = 0.0;
-  for (int q = L; q >= 1; --q) {
-    // C(L, q) from C(L, q + 1): * (q + 1) / (L - q), exact in doubles
-    if (q < L) binom = binom * (double)(q + 1) / (double)(L - q);
-    const double w = (q & 1) ? binom : -binom;
-    g = fma(w, hk[(size_t)((s - q) % levels) * fstride], g);
-  }
+  const double* w = wtab + L * kWarmCols;
+  double g = 0.0;
+  for (int q = L; q >= 1; --q)  // oldest point first
+    g = fma(w[q - 1], hk[(size_t)((s - q) % levels) * fstride], g);
   psi[p] = g;
 }
 
@@ -2180,14 +2188,17 @@ hipError_t launch_batch_mixed(const SorConfig& c, const BatchMember* mem, int co
   return hipErrorInvalidValue;
 }
 
-int resid_blocks() { return kResidBlocks; }
+int resid_blocks(int n) {
+  const dim3 g = resid_grid(n);
+  return (int)(g.x * g.y);
+}
 
 hipError_t launch_resid64(const double* psi, const double* F, float* R32, float* d32, int n,
                           int pitch, PoissonCtl* ctl, double* part, hipStream_t st,
                           long long sweeps_done) {
-  const int blocks = std::min(kResidBlocks, n - 2);  // one interior row per block and pass
-  hipLaunchKernelGGL(k_resid64, dim3(blocks), dim3(kBlock), 0, st, psi, F, R32, d32, n, pitch,
-                     ctl, part);
+  const dim3 g = resid_grid(n);
+  const int blocks = (int)(g.x * g.y);
+  hipLaunchKernelGGL(k_resid64, g, dim3(kBlock), 0, st, psi, F, R32, d32, n, pitch, ctl, part);
   hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, st, ctl, part, blocks, sweeps_done);
   return hipGetLastError();
 }
@@ -2365,9 +2376,9 @@ hipError_t launch_copy_interior(const double* src, double* dst, int n, int pitch
 }
 
 hipError_t launch_warm(double* psi, double* hist, size_t fstride, int n, int pitch, int stage,
-                       int levels, const long long* count, hipStream_t st) {
+                       int levels, const long long* count, const double* wtab, hipStream_t st) {
   hipLaunchKernelGGL(k_warm, grid2d(n, n), dim3(kBlock), 0, st, psi, hist, fstride, n, pitch,
-                     stage, levels, count);
+                     stage, levels, count, wtab);
   return hipGetLastError();
 }
 

@@ -118,9 +118,11 @@ struct Member {
   // in hist (5 * warm pitched fields, hist_stride doubles apart; stage k's
   // slot r at (k - 1) * warm + r) with the count of steps on file in warm_cnt.
   int warm = 1;
+  int warm_deg = 0;          // degree of the polynomial through the warm steps on file
   double* hist = nullptr;
   size_t hist_stride = 0;
   long long* warm_cnt = nullptr;
+  double* warm_w = nullptr;  // device: row L = weights for L steps on file (L <= warm)
   std::vector<MgLevel> mg;  // multigrid hierarchy (allocated for every cavity)
   std::vector<MgLevel32> mg32;  // FP32 hierarchy (mixed cavities)
   // host-side state
@@ -262,6 +264,7 @@ int derive(const cavity_params& p, Member& m) {
            : p.fixed_sweeps > 0              ? CAVITY_WARM_PREVIOUS
            : p.precision == CAVITY_MIXED     ? CAVITY_WARM_LEVELS_MIXED
                                              : CAVITY_WARM_LEVELS_FP64;
+  m.warm_deg = m.warm >= 2 ? m.warm - 1 : 0;
   m.tol = p.poisson_tol > 0 ? p.poisson_tol : 1e-10;
   m.max_sweeps = p.poisson_max_sweeps > 0 ? p.poisson_max_sweeps : 200LL * p.n;
   if (p.sor_omega > 0) {
@@ -310,24 +313,34 @@ int derive(const cavity_params& p, Member& m) {
     m.cfg64 = {64, 64, 4, 512, 0};
     m.cfg32 = {88, 56, 5, 1024, 1};
   }
-  // Residual checks every n/10 sweeps (4 to 256): a solve needs O(n) sweeps,
-  // so the overshoot past convergence stays a fixed small fraction while the
-  // check launches (and their decision kernels) stay rare.  Measured on the
-  // time step at 513^2 to 2049^2 against n/16 (at most 64): equal at 513^2,
-  // 1 % faster at 1024^2, 3 % at 2049^2.
+  // Residual checks every n/10 sweeps (4 to 256) for solves started from the
+  // previous stage's psi: a solve needs O(n) sweeps, so the overshoot past
+  // convergence stays a fixed small fraction while the check launches (and
+  // their decision kernels) stay rare.  Measured on the time step at 513^2 to
+  // 2049^2 against n/16 (at most 64): equal at 513^2, 1 % faster at 1024^2,
+  // 3 % at 2049^2.  Extrapolated starts need about half as many sweeps, and
+  // checks every n/24 sweeps (rounded up to whole launch pairs: 50 at 1024^2)
+  // are the fastest (1024^2, 1000 steps, Re 1e4 / 3e4: 30.5 / 31.3
+  // Mcell-steps/s against 29.7 / 30.5 with n/10 = 110; 30, 70 and 160 sweeps
+  // in between or below).
   // Mixed: 0.6 (n - 1) FP32 sweeps per refinement round.  A round reduces
   // the FP64 residual only about as far as the FP32 correction is accurate,
   // so sweeps beyond that are wasted; measured with the default relaxation
   // (factors 0.3 ... 3): the fastest steps at 1024^2 and at 4096^2 (23.9 and
-  // 11.2 Mcell-steps/s against 17.8 and 5.1 with 1.5 (n - 1)).
-  set_schedule(m, std::min(256, std::max(4, p.n / 10)), (int)std::ceil(0.6 * (p.n - 1)));
+  // 11.2 Mcell-steps/s against 17.8 and 5.1 with 1.5 (n - 1)).  With
+  // extrapolated starts, 0.3 (n - 1) (1024^2, Re 3e4, 1000 steps: 84.8
+  // Mcell-steps/s against 70.4; 200, 400, 500 and 800 sweeps: 70.5, 75.8,
+  // 62.8, 55.3).
+  const bool extrap = m.warm >= 2;
+  set_schedule(m, std::min(256, std::max(4, p.n / (extrap ? 24 : 10))),
+               (int)std::ceil((extrap ? 0.3 : 0.6) * (p.n - 1)));
   return CAVITY_OK;
 }
 
 size_t part_doubles(int n) {
   // two maxima per block of a checking launch or of the residual kernel;
   // a resident solve keeps two check slots of two maxima per tile
-  return 4 * (size_t)std::max(cav::sor_max_blocks(n), cav::resid_blocks());
+  return 4 * (size_t)std::max(cav::sor_max_blocks(n), cav::resid_blocks(n));
 }
 
 size_t flag_bytes() { return (size_t)cav::kMaxBatchGrid * cav::kFlagStride * sizeof(unsigned int); }
@@ -359,6 +372,76 @@ size_t mg32_bytes(int n) {
   return b;
 }
 
+// Extrapolation weights of the warm starts.  Row L (2 <= L <= warm) holds w_q,
+// q = 1 ... L: the start is sum_q w_q psi(step - q) for the polynomial of
+// degree min(d, L - 1) through the L steps on file (least squares below L - 1).
+constexpr int kWarmRows = CAVITY_WARM_LEVELS_MAX + 1;
+using cav::kWarmCols;
+static_assert(kWarmCols >= CAVITY_WARM_LEVELS_MAX, "a weight row holds every level");
+
+// w_q for L points at -1 ... -L, degree d <= L - 1, evaluated at 0.  d = L - 1
+// interpolates: the weights are (-1)^(q+1) C(L, q), exact in doubles.  Below,
+// the least-squares polynomial, through a QR factorisation (modified
+// Gram-Schmidt, long double) of the Vandermonde matrix in the centred abscissa
+// s = (2q - L - 1) / (L - 1): p(0) = v0^T R^-1 Q^T y for the monomials v0 at
+// s0 = -(L + 1) / (L - 1), so w = Q R^-T v0.
+void warm_weights(int L, int d, double* w) {
+  if (d >= L - 1) {
+    double b = 1.0;
+    for (int q = L; q >= 1; --q) {
+      if (q < L) b = b * (q + 1) / (L - q);
+      w[q - 1] = (q & 1) ? b : -b;
+    }
+    return;
+  }
+  long double Q[kWarmCols][kWarmCols] = {}, R[kWarmCols][kWarmCols] = {};
+  for (int q = 1; q <= L; ++q) {
+    const long double s = (long double)(2 * q - L - 1) / (L - 1);
+    long double pw = 1;
+    for (int k = 0; k <= d; ++k) {
+      Q[q - 1][k] = pw;
+      pw *= s;
+    }
+  }
+  for (int k = 0; k <= d; ++k) {
+    for (int j = 0; j < k; ++j) {
+      long double dot = 0;
+      for (int q = 0; q < L; ++q) dot += Q[q][j] * Q[q][k];
+      R[j][k] = dot;
+      for (int q = 0; q < L; ++q) Q[q][k] -= dot * Q[q][j];
+    }
+    long double nrm = 0;
+    for (int q = 0; q < L; ++q) nrm += Q[q][k] * Q[q][k];
+    nrm = sqrtl(nrm);
+    R[k][k] = nrm;
+    for (int q = 0; q < L; ++q) Q[q][k] /= nrm;
+  }
+  const long double s0 = -(long double)(L + 1) / (L - 1);
+  long double z[kWarmCols], pw = 1;
+  for (int k = 0; k <= d; ++k) {  // R^T z = v0
+    long double v = pw;
+    for (int j = 0; j < k; ++j) v -= R[j][k] * z[j];
+    z[k] = v / R[k][k];
+    pw *= s0;
+  }
+  for (int q = 0; q < L; ++q) {
+    long double v = 0;
+    for (int k = 0; k <= d; ++k) v += Q[q][k] * z[k];
+    w[q] = (double)v;
+  }
+}
+
+// Upload member m's weight table (enqueued on st; the host table stays valid
+// until the stream has copied it: synchronised before returning).
+hipError_t upload_warm_weights(const Member& m, hipStream_t st) {
+  double tab[kWarmRows * kWarmCols] = {};
+  for (int L = 2; L <= m.warm; ++L)
+    warm_weights(L, std::min(m.warm_deg, L - 1), tab + L * kWarmCols);
+  hipError_t e = hipMemcpyAsync(m.warm_w, tab, sizeof tab, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
 size_t member_bytes(const Member& m) {
   const size_t f64 = align_up((size_t)m.n * m.pitch * sizeof(double));
   const size_t f32 = align_up((size_t)m.n * m.pitch * sizeof(float));
@@ -371,7 +454,9 @@ size_t member_bytes(const Member& m) {
   b += align_up(4 * sizeof(double));
   b += mg_bytes(m.n);
   if (m.mixed) b += mg32_bytes(m.n);
-  if (m.warm >= 2) b += 5 * (size_t)m.warm * f64 + align_up(sizeof(long long));
+  if (m.warm >= 2)
+    b += 5 * (size_t)m.warm * f64 + align_up(sizeof(long long)) +
+         align_up(kWarmRows * kWarmCols * sizeof(double));
   return b;
 }
 
@@ -405,6 +490,7 @@ void carve(Member& m, char*& cur) {
     m.hist_stride = f64 / sizeof(double);
     m.hist = reinterpret_cast<double*>(take(5 * (size_t)m.warm * f64));
     m.warm_cnt = reinterpret_cast<long long*>(take(align_up(sizeof(long long))));
+    m.warm_w = reinterpret_cast<double*>(take(align_up(kWarmRows * kWarmCols * sizeof(double))));
   }
   const std::vector<int> v = mg_sizes(m.n);
   m.mg.assign(v.size(), MgLevel{});
@@ -1004,7 +1090,7 @@ int enqueue_stage_one(cavity_s* h, Member& m, int stage) {
     // the extrapolation
     if (m.warm >= 2)
       HIP_TRY(h, cav::launch_warm(m.psi, m.hist, m.hist_stride, m.n, m.pitch, stage, m.warm,
-                                  m.warm_cnt, h->st));
+                                  m.warm_cnt, m.warm_w, h->st));
     return CAVITY_OK;
   }
 }
@@ -1345,11 +1431,12 @@ bool cache_lookup(const char* path, const std::string& key, cavity_tuning* t) {
                            "\"threads\": %d, \"tile_x32\": %d, \"tile_y32\": %d, "
                            "\"sweeps_per_launch32\": %d, \"threads32\": %d, "
                            "\"check_every\": %d, \"inner_sweeps\": %d, \"xcd_bands\": %d, "
-                           "\"solver\": %d, \"sor_omega\": %lf",
+                           "\"solver\": %d, \"sor_omega\": %lf, \"warm_degree\": %d",
                            &r.tile_x, &r.tile_y, &r.sweeps_per_launch, &r.threads, &r.tile_x32,
                            &r.tile_y32, &r.sweeps_per_launch32, &r.threads32, &r.check_every,
-                           &r.inner_sweeps, &r.xcd_bands, &r.solver, &r.sor_omega);
-    if (got == 13) {
+                           &r.inner_sweeps, &r.xcd_bands, &r.solver, &r.sor_omega,
+                           &r.warm_degree);
+    if (got == 14) {
       *t = r;
       found = true;  // the last matching line wins
     }
@@ -1366,10 +1453,10 @@ void cache_store(const char* path, const std::string& key, const cavity_tuning& 
           "{\"key\": \"%s\", \"tile_x\": %d, \"tile_y\": %d, \"sweeps_per_launch\": %d, "
           "\"threads\": %d, \"tile_x32\": %d, \"tile_y32\": %d, \"sweeps_per_launch32\": %d, "
           "\"threads32\": %d, \"check_every\": %d, \"inner_sweeps\": %d, "
-          "\"xcd_bands\": %d, \"solver\": %d, \"sor_omega\": %.17g}\n",
+          "\"xcd_bands\": %d, \"solver\": %d, \"sor_omega\": %.17g, \"warm_degree\": %d}\n",
           key.c_str(), t.tile_x, t.tile_y, t.sweeps_per_launch, t.threads, t.tile_x32,
           t.tile_y32, t.sweeps_per_launch32, t.threads32, t.check_every, t.inner_sweeps,
-          t.xcd_bands, t.solver, t.sor_omega);
+          t.xcd_bands, t.solver, t.sor_omega, t.warm_degree);
   fclose(f);
 }
 
@@ -1489,8 +1576,9 @@ int cavity_create(const cavity_params* p, int32_t count, void* d_ws, size_t ws_b
     if (cav::launch_zero(m.ctl, sizeof(cav::PoissonCtl), h->st) != hipSuccess)
       return bail(fail(CAVITY_EHIP, "zero fill failed"));
     // no step on file yet
-    if (m.warm_cnt && cav::launch_zero(m.warm_cnt, sizeof(long long), h->st) != hipSuccess)
-      return bail(fail(CAVITY_EHIP, "zero fill failed"));
+    if (m.warm_cnt && (cav::launch_zero(m.warm_cnt, sizeof(long long), h->st) != hipSuccess ||
+                       upload_warm_weights(m, h->st) != hipSuccess))
+      return bail(fail(CAVITY_EHIP, "warm-start setup failed"));
     for (int k = 0; k < 4; ++k)
       if (cav::launch_fill(m.w[k], m.n, m.pitch, 0.0, h->st) != hipSuccess)
         return bail(fail(CAVITY_EHIP, "fill failed"));
@@ -1872,6 +1960,7 @@ int cavity_get_tuning(cavity_t h, int32_t idx, cavity_tuning* t) {
   t->xcd_bands = m.cfg64.xcd_bands;
   t->solver = m.solver;
   t->sor_omega = m.relax;
+  t->warm_degree = m.warm >= 2 ? m.warm_deg : 0;
   return CAVITY_OK;
 }
 
@@ -1917,6 +2006,13 @@ int cavity_set_tuning(cavity_t h, int32_t idx, const cavity_tuning* t) {
     return fail(CAVITY_EINVAL, "the multigrid solver runs in stream execution");
   if (t->solver == CAVITY_SOLVER_MG && m.fixed > 0)
     return fail(CAVITY_EINVAL, "fixed_sweeps runs the SOR solver only");
+  if (t->warm_degree < 0 || (t->warm_degree > 0 && (m.warm < 2 || t->warm_degree >= m.warm)))
+    return fail(CAVITY_EINVAL, "warm_degree %d outside [1, %d]", t->warm_degree, m.warm - 1);
+  if (t->warm_degree > 0 && t->warm_degree != m.warm_deg) {
+    m.warm_deg = t->warm_degree;
+    HIP_TRY(h, hipSetDevice(h->device));
+    HIP_TRY(h, upload_warm_weights(m, h->st));
+  }
   m.solver = t->solver;
   m.cfg64 = c64;
   m.cfg32 = c32;

@@ -96,19 +96,21 @@ def test_workspace_bytes_scales_with_grid(binding):
 
 
 def test_workspace_bytes_holds_the_warm_start_history(binding):
-    """Extrapolated warm starts keep 5 fields (one per SSPRK stage) per level."""
+    """Extrapolated warm starts keep 5 fields (one per SSPRK stage) per level,
+    plus a step counter and the weight table (256 + 768 bytes)."""
     P = binding.Params
     field = 1024 * 1024 * 8   # 1024 nodes a side, pitch 1024
+    extra = 256 + 768
     prev = binding.cavity_workspace_bytes([P(n=1024, warm_start=1).to_c()])
     for levels in range(2, binding.CAVITY_WARM_LEVELS_MAX + 1):
         got = binding.cavity_workspace_bytes([P(n=1024, warm_start=levels).to_c()])
-        assert got - prev == 5 * levels * field + 256
+        assert got - prev == 5 * levels * field + extra
     default = binding.cavity_workspace_bytes([P(n=1024).to_c()])
-    assert default - prev == 5 * binding.CAVITY_WARM_LEVELS_FP64 * field + 256
+    assert default - prev == 5 * binding.CAVITY_WARM_LEVELS_FP64 * field + extra
     mixed_prev = binding.cavity_workspace_bytes(
         [P(n=1024, precision=binding.CAVITY_MIXED, warm_start=1).to_c()])
     mixed = binding.cavity_workspace_bytes([P(n=1024, precision=binding.CAVITY_MIXED).to_c()])
-    assert mixed - mixed_prev == 5 * binding.CAVITY_WARM_LEVELS_MIXED * field + 256
+    assert mixed - mixed_prev == 5 * binding.CAVITY_WARM_LEVELS_MIXED * field + extra
     # the coupled mode starts every stage from the previous stage's psi
     fixed = binding.cavity_workspace_bytes([P(n=1024, fixed_sweeps=8).to_c()])
     assert fixed == prev

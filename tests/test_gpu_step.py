@@ -87,6 +87,30 @@ def test_step_parity_1024_paper_time_step(cm):
     assert ep <= PARITY and ew <= PARITY, (ep, ew)
 
 
+@pytest.mark.parametrize("degree", [2, 3, 5])
+def test_least_squares_starts_at_parity(cm, degree):
+    """Starts from the least-squares polynomial of a lower degree through the
+    eight steps on file: the same parity with the oracle; a degree that the
+    steps on file cannot carry is rejected."""
+    n, re, steps = 257, 1.0e4, 24
+    print(f"[warm degree] n={n} degree={degree}", flush=True)
+    c = cm.Cavity(cm.Params(n=n, re=re, warm_start=8))
+    assert c.tuning()["warm_degree"] == 7
+    c.set_tuning(warm_degree=degree)
+    assert c.tuning()["warm_degree"] == degree
+    with pytest.raises(cm.CavityError):
+        c.set_tuning(warm_degree=8)
+    st = c.step(steps)[0]
+    psi, omega, _, _ = c.fields()
+    c.close()
+    ref = CavityOracle(n, re)
+    ref.step(steps)
+    ep, ew = _rel(psi, ref.psi), _rel(omega, ref.omega)
+    print(f"  psi_rel={ep:.3e} omega_rel={ew:.3e} sweeps/step={st['sweeps_last_step']}")
+    assert st["status"] == 0
+    assert ep <= PARITY and ew <= PARITY, (ep, ew)
+
+
 def test_walls_zero_and_bitwise_repeatable(cm):
     n, re, steps = 130, 3000.0, 15
     print(f"[repeatable] n={n}", flush=True)
