@@ -68,12 +68,14 @@ enum cavity_precision {
  * sweeps, not the result beyond that tolerance.  Values of
  * cavity_params.warm_start:
  *   0 (CAVITY_WARM_DEFAULT): for converged solves CAVITY_WARM_LEVELS_FP64
- *     levels in FP64 and CAVITY_WARM_LEVELS_MIXED in mixed precision (the
- *     fastest on the 1024^2 workloads: more levels leave the solves' own
- *     tolerance-level differences, amplified by the extrapolation weights,
- *     as the larger part of the start's error), CAVITY_WARM_PREVIOUS in the
- *     coupled mode (fixed_sweeps > 0, whose fixed iteration starts from the
- *     previous stage's psi by definition);
+ *     levels in FP64 (interpolated) and CAVITY_WARM_LEVELS_MIXED in mixed
+ *     precision (the least-squares polynomial of degree
+ *     CAVITY_WARM_DEGREE_MIXED through them), the fastest on the 1024^2
+ *     workloads (more levels, or a higher degree, pass on more of the
+ *     solves' own tolerance-level differences, amplified by the
+ *     extrapolation weights); CAVITY_WARM_PREVIOUS in the coupled mode
+ *     (fixed_sweeps > 0, whose fixed iteration starts from the previous
+ *     stage's psi by definition);
  *   1 (CAVITY_WARM_PREVIOUS): the psi of the stage before;
  *   2 ... 8 (levels): the polynomial through the same stage's solutions of
  *     the last `levels` steps, evaluated at the current step.  Consecutive
@@ -86,7 +88,8 @@ enum cavity_warm_start {
   CAVITY_WARM_DEFAULT = 0,
   CAVITY_WARM_PREVIOUS = 1,
   CAVITY_WARM_LEVELS_FP64 = 7,
-  CAVITY_WARM_LEVELS_MIXED = 6,
+  CAVITY_WARM_LEVELS_MIXED = 8,
+  CAVITY_WARM_DEGREE_MIXED = 5,
   CAVITY_WARM_LEVELS_MAX = 8
 };
 
@@ -315,8 +318,10 @@ typedef struct cavity_tuning {
                                     L steps on file, 1 <= d <= L - 1; d = L - 1
                                     interpolates them, a lower degree is their
                                     least-squares fit, which passes on less of the
-                                    solves' own tolerance-level differences.  0 in
-                                    cavity_set_tuning keeps the current degree;
+                                    solves' own tolerance-level differences
+                                    (default: L - 1 in FP64, at most
+                                    CAVITY_WARM_DEGREE_MIXED in mixed precision).
+                                    0 in cavity_set_tuning keeps the current degree;
                                     cavity_get_tuning reports 0 when the cavity
                                     has no extrapolated starts                      */
 } cavity_tuning;

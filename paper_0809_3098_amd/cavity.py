@@ -42,7 +42,8 @@ CAVITY_SOLVER_MG = 1
 CAVITY_WARM_DEFAULT = 0
 CAVITY_WARM_PREVIOUS = 1
 CAVITY_WARM_LEVELS_FP64 = 7
-CAVITY_WARM_LEVELS_MIXED = 6
+CAVITY_WARM_LEVELS_MIXED = 8
+CAVITY_WARM_DEGREE_MIXED = 5
 CAVITY_WARM_LEVELS_MAX = 8
 
 _STATUS_NAMES = {0: "CAVITY_OK", -1: "CAVITY_EINVAL", -2: "CAVITY_ENOMEM", -3: "CAVITY_EHIP",

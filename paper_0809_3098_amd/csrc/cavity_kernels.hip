@@ -1709,9 +1709,10 @@ __global__ void k_ctl_reset(PoissonCtl* c, double relax, double tol_hat, long lo
 // r = g(psi) - psi in FP64 on interior nodes, reduced to max |r| for the solve
 // decision; with R32 != nullptr also stored as float for the FP32 correction
 // solve, whose correction d32 then starts from zero.  A block of 256 threads
-// takes a tile of 64 x 16 interior nodes, each thread four rows of one column
-// with all loads issued together; its two maxima go to the partial array
-// (one pair per block), which k_decide reduces.
+// takes a tile of 64 x 16 interior nodes; a thread takes four consecutive rows
+// of one column and loads the six rows of psi they touch once (all loads
+// issued together); the block's two maxima go to the partial array (one pair
+// per block), which k_decide reduces.
 constexpr int kResidTileX = 64, kResidTileY = 16;
 
 inline dim3 resid_grid(int n) {
@@ -1727,23 +1728,34 @@ __global__ __launch_bounds__(kBlock) void k_resid64(const double* __restrict__ p
   if (ctl->state != SOLVE_RUN) return;
   double rmax = 0.0, pmax = 0.0;
   const int i = 1 + blockIdx.x * kResidTileX + (threadIdx.x & 63);
-  const int jb = 1 + blockIdx.y * kResidTileY + (threadIdx.x >> 6);
+  const int j0 = 1 + blockIdx.y * kResidTileY + 4 * (threadIdx.x >> 6);
+  if (i <= n - 2 && j0 <= n - 2) {
+    // rows j0 - 1 ... j0 + 4 (those inside the grid), columns i - 1, i, i + 1
+    double w[6], c[6], e[6];
 #pragma unroll
-  for (int q = 0; q < kResidTileY / 4; ++q) {
-    const int j = jb + 4 * q;
-    if (i > n - 2 || j > n - 2) continue;
-    const size_t p = (size_t)j * pitch + i;
-    const double s4 = (psi[p + 1] + psi[p - 1]) + (psi[p + pitch] + psi[p - pitch]);
-    const double sd = (psi[p + pitch + 1] + psi[p + pitch - 1]) +
-                      (psi[p - pitch + 1] + psi[p - pitch - 1]);
-    const double g = fma(0.2, s4, fma(0.05, sd, F[p]));
-    const double r = g - psi[p];
-    if (R32) {
-      R32[p] = (float)r;
-      d32[p] = 0.0f;
+    for (int r = 0; r < 6; ++r) {
+      const int j = j0 - 1 + r;
+      const size_t q = (size_t)min(j, n - 1) * pitch + i;
+      w[r] = psi[q - 1];
+      c[r] = psi[q];
+      e[r] = psi[q + 1];
     }
-    rmax = fmax(rmax, mag(r));
-    pmax = fmax(pmax, mag(psi[p]));
+#pragma unroll
+    for (int r = 1; r <= 4; ++r) {
+      const int j = j0 - 1 + r;
+      if (j > n - 2) break;
+      const size_t p = (size_t)j * pitch + i;
+      const double s4 = (e[r] + w[r]) + (c[r + 1] + c[r - 1]);
+      const double sd = (e[r + 1] + w[r + 1]) + (e[r - 1] + w[r - 1]);
+      const double g = fma(0.2, s4, fma(0.05, sd, F[p]));
+      const double res = g - c[r];
+      if (R32) {
+        R32[p] = (float)res;
+        d32[p] = 0.0f;
+      }
+      rmax = fmax(rmax, mag(res));
+      pmax = fmax(pmax, mag(c[r]));
+    }
   }
   // per-block maxima only; k_decide follows on the stream
   block_max2<kBlock>(rmax, pmax);

@@ -264,7 +264,13 @@ int derive(const cavity_params& p, Member& m) {
            : p.fixed_sweeps > 0              ? CAVITY_WARM_PREVIOUS
            : p.precision == CAVITY_MIXED     ? CAVITY_WARM_LEVELS_MIXED
                                              : CAVITY_WARM_LEVELS_FP64;
-  m.warm_deg = m.warm >= 2 ? m.warm - 1 : 0;
+  // FP64: the interpolating polynomial; mixed: a least-squares fit of degree at
+  // most 5 (1024^2, Re 3e4, 1000 steps: 95.7 Mcell-steps/s with 8 steps and
+  // degree 5, 93.1 with degree 4, 85.4 interpolating 6 steps, 60.3 with degree
+  // 3; in FP64 the fits were slower: 25.9 with 8 steps and degree 5 against
+  // 30.5 interpolating 7)
+  m.warm_deg = m.warm < 2 ? 0 : m.mixed ? std::min(m.warm - 1, (int)CAVITY_WARM_DEGREE_MIXED)
+                                        : m.warm - 1;
   m.tol = p.poisson_tol > 0 ? p.poisson_tol : 1e-10;
   m.max_sweeps = p.poisson_max_sweeps > 0 ? p.poisson_max_sweeps : 200LL * p.n;
   if (p.sor_omega > 0) {

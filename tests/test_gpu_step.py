@@ -94,6 +94,9 @@ def test_least_squares_starts_at_parity(cm, degree):
     steps on file cannot carry is rejected."""
     n, re, steps = 257, 1.0e4, 24
     print(f"[warm degree] n={n} degree={degree}", flush=True)
+    m = cm.Cavity(cm.Params(n=n, re=re, precision=cm.CAVITY_MIXED))
+    assert m.tuning()["warm_degree"] == cm.CAVITY_WARM_DEGREE_MIXED  # the mixed default
+    m.close()
     c = cm.Cavity(cm.Params(n=n, re=re, warm_start=8))
     assert c.tuning()["warm_degree"] == 7
     c.set_tuning(warm_degree=degree)
