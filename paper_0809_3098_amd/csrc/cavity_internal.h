@@ -39,6 +39,7 @@ struct alignas(128) PoissonCtl {
   long long sweeps_per_check; // sweeps between two checks
   double floor_ulps;          // > 0: a residual within this many ulps of max |psi| is the
                               // rounding floor and stops the solve (floor-limited)
+  int gs_open;                // 1: relax with 1 (Gauss-Seidel) until the first check
   int floor_limited;
   int werror;                 // 1: a wait of a resident solve timed out
   // Totals over every solve since the handle was created (never reset by a
@@ -134,9 +135,13 @@ hipError_t launch_stage(const double* psi, const float* psi32, const double* w0,
                         double* p_out, int n, int pitch, const StageArgs& a, hipStream_t st);
 
 // Reset a solve's control block (a kernel, so it can live in a graph).
+// gs_steps: if not null and at least two steps are on file there (the count of
+// an extrapolated warm start), the solve opens with Gauss-Seidel sweeps
+// (relaxation 1) and switches to `relax` at its first check after a sweep.
 hipError_t launch_ctl_reset(PoissonCtl* ctl, double relax, double tol_hat,
                             long long max_sweeps, long long stall_window,
-                            long long sweeps_per_check, hipStream_t st, double floor_ulps = 0.0);
+                            long long sweeps_per_check, hipStream_t st, double floor_ulps = 0.0,
+                            const long long* gs_steps = nullptr);
 
 // One launch of `cfg.s` four-colour sweeps, psi_in -> psi_out (ping-pong).
 // check != 0: also the residual of the result and the solve decision.

@@ -67,6 +67,11 @@ __device__ void decide(PoissonCtl* c, double r, double pm, long long sweeps_done
   c->total_sweeps += sweeps_done;
   c->last = r;
   c->psimax = pm;
+  // an opening of Gauss-Seidel sweeps ends at the first check after a sweep
+  if (c->gs_open && c->sweeps > 0) {
+    c->gs_open = 0;
+    c->relax = c->relax_sor;
+  }
   int st = SOLVE_RUN;
   if (!(r <= DBL_MAX)) {
     st = SOLVE_NONFINITE;
@@ -1685,12 +1690,14 @@ __global__ __launch_bounds__(kBlock) void k_thom(const double* __restrict__ psi,
 // ---------------------------------------------------------------------------
 __global__ void k_ctl_reset(PoissonCtl* c, double relax, double tol_hat, long long max_sweeps,
                             long long stall_window, long long sweeps_per_check,
-                            double floor_ulps) {
+                            double floor_ulps, const long long* gs_steps) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int gs_open = (gs_steps && *gs_steps >= 2) ? 1 : 0;
   c->state = SOLVE_RUN;
   c->phase = 0;
   c->polish_left = 0;
-  c->relax = relax;
+  c->gs_open = gs_open;
+  c->relax = gs_open ? 1.0 : relax;
   c->relax_sor = relax;
   c->tol_hat = tol_hat;
   c->best = (double)INFINITY;
@@ -2088,9 +2095,9 @@ hipError_t launch_stage(const double* psi, const float* psi32, const double* w0,
 
 hipError_t launch_ctl_reset(PoissonCtl* ctl, double relax, double tol_hat, long long max_sweeps,
                             long long stall_window, long long sweeps_per_check, hipStream_t st,
-                            double floor_ulps) {
+                            double floor_ulps, const long long* gs_steps) {
   hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, ctl, relax, tol_hat, max_sweeps,
-                     stall_window, sweeps_per_check, floor_ulps);
+                     stall_window, sweeps_per_check, floor_ulps, gs_steps);
   return hipGetLastError();
 }
 

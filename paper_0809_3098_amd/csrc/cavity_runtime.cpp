@@ -571,7 +571,22 @@ constexpr double kMgFloorUlps = 8.0;
 // ---------------------------------------------------------------------------
 long long unit_sweeps(const Member& m);
 
-int reset_ctl(cavity_s* h, Member& m) {
+// FP64 SOR solves of a time step's stages that start from an extrapolation
+// (two or more steps on file: decided on the device from the warm-start
+// count, so a captured step graph does the same) open with Gauss-Seidel
+// sweeps up to their first check.  The extrapolation's error is small but
+// rough in space (largest next to the lid corners), so the start's residual
+// is large (257^2, Re 1e4, step 100: error 3e-11, residual 6.7e-6 in
+// vorticity units); over-relaxation damps rough components only by about
+// w - 1 per sweep, Gauss-Seidel by a large factor.  Measured with the
+// oracle's four-colour sweep on those starts: 350 sweeps to 1e-10, 130 with
+// 10 Gauss-Seidel sweeps first, 90 with 20, 80 with 40.
+bool gs_opening(const Member& m) {
+  return m.warm >= 2 && !m.mixed && m.solver == CAVITY_SOLVER_SOR && m.fixed == 0;
+}
+
+// stage_solve: the solve of an SSPRK stage (its start may be an extrapolation).
+int reset_ctl(cavity_s* h, Member& m, bool stage_solve) {
   const double tol_hat = m.tol * 0.3 * m.h * m.h;  // (g - psi) = (3 h^2 / 10) r
   const long long spc = unit_sweeps(m);
   // multigrid halves the residual every cycle until the rounding floor:
@@ -580,7 +595,8 @@ int reset_ctl(cavity_s* h, Member& m) {
   const bool mg = m.solver == CAVITY_SOLVER_MG;
   const long long stall = mg ? 8LL * spc : m.stall_window;
   HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, stall, spc, h->st,
-                                   mg ? kMgFloorUlps : 0.0));
+                                   mg ? kMgFloorUlps : 0.0,
+                                   stage_solve && gs_opening(m) ? m.warm_cnt : nullptr));
   return CAVITY_OK;
 }
 
@@ -748,13 +764,14 @@ bool resident_config(const cavity_s* h, const Member& m, cav::SorConfig* c) {
 // initial check).  Rounds per check follow the member's check spacing, but
 // at least half the tile grid's width plus one, so that no block can run
 // far enough ahead to reuse a partial-maximum slot block 0 is still reading.
-int enqueue_resident(cavity_s* h, Member& m, const cav::SorConfig& c) {
+int enqueue_resident(cavity_s* h, Member& m, const cav::SorConfig& c, bool stage_solve) {
   const int tiles = std::max((m.n + c.tx - 1) / c.tx, (m.n + c.ty - 1) / c.ty);
   const long long spc = 2LL * m.cfg64.s * m.pairs_per_check;
   const int P = std::max<int>({3, tiles / 2 + 1, (int)((spc + c.s - 1) / c.s)});
   const double tol_hat = m.tol * 0.3 * m.h * m.h;
   HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, m.stall_window,
-                                   (long long)P * c.s, h->st));
+                                   (long long)P * c.s, h->st, 0.0,
+                                   stage_solve && gs_opening(m) ? m.warm_cnt : nullptr));
   HIP_TRY(h, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, m.part,
                                  h->st));
   const long long spin = 10LL * 100000000LL;  // 10 s of the 100 MHz wall clock
@@ -776,11 +793,11 @@ int solve_members(cavity_s* h, const std::vector<int>& idx, bool state_solve = t
     StreamScope sc(h, member_stream(h, k));
     cav::SorConfig rcfg;
     if (resident_config(h, m, &rcfg)) {
-      if ((rc = enqueue_resident(h, m, rcfg)) != CAVITY_OK) return rc;
+      if ((rc = enqueue_resident(h, m, rcfg, stage > 0)) != CAVITY_OK) return rc;
       resident.push_back(k);
       continue;
     }
-    if ((rc = reset_ctl(h, m)) != CAVITY_OK) return rc;
+    if ((rc = reset_ctl(h, m, stage > 0)) != CAVITY_OK) return rc;
     if ((rc = enqueue_initial_check(h, m)) != CAVITY_OK) return rc;
     active.push_back(k);
   }
@@ -990,7 +1007,8 @@ int enqueue_batch_solve(cavity_s* h) {
   for (Member& m : h->m) {
     const double tol_hat = m.tol * 0.3 * m.h * m.h;
     HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, m.stall_window,
-                                     batch_check_sweeps(h), h->st));
+                                     batch_check_sweeps(h), h->st, 0.0,
+                                     !h->mixed && gs_opening(m) ? m.warm_cnt : nullptr));
     if (!h->mixed)
       HIP_TRY(h, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, m.part,
                                      h->st));

@@ -24,7 +24,10 @@ def test_autotune_single_then_cached(cm, tmp_path):
     n, re = 257, 2000.0
     cache = str(tmp_path / "tune.jsonl")
     print(f"[autotune] n={n}", flush=True)
-    c = cm.Cavity(cm.Params(n=n, re=re))
+    # solves to 1e-11: ten steps from rest leave psi small, and the 1e-11 bar
+    # then needs a tolerance below the default (see the six-cavity test in
+    # test_gpu_batch)
+    c = cm.Cavity(cm.Params(n=n, re=re, poisson_tol=1e-11))
     c.step(2, want_stats=False)
     before = c.fields()
     t1 = c.autotune(0, cache)
