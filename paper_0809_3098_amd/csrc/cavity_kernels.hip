@@ -60,57 +60,6 @@ __device__ inline double mag(double r) {
   return (r != r) ? (double)INFINITY : r;
 }
 
-// The decision of a Poisson solve after one residual check (see PoissonCtl).
-// r is max |g - psi| in the units of the relaxation formula.
-__device__ void decide(PoissonCtl* c, double r, double pm, long long sweeps_done) {
-  c->sweeps += sweeps_done;
-  c->total_sweeps += sweeps_done;
-  c->last = r;
-  c->psimax = pm;
-  // an opening of Gauss-Seidel sweeps ends at the first check after a sweep
-  if (c->gs_open && c->sweeps > 0) {
-    c->gs_open = 0;
-    c->relax = c->relax_sor;
-  }
-  int st = SOLVE_RUN;
-  if (!(r <= DBL_MAX)) {
-    st = SOLVE_NONFINITE;
-  } else if (r <= c->tol_hat) {
-    st = SOLVE_CONVERGED;
-  } else if (c->floor_ulps > 0.0 && r <= c->floor_ulps * DBL_EPSILON * pm) {
-    // The residual is at the rounding level of psi itself: no iteration can
-    // lower it further (multigrid reaches it in a few cycles).
-    st = SOLVE_FLOOR;
-    c->floor_limited = 1;
-  } else {
-    if (r < 0.5 * c->best) {
-      c->best = r;
-      c->best_at = c->sweeps;
-    }
-    if (c->phase == 0) {
-      if (c->sweeps - c->best_at >= c->stall_window) {
-        // Over-relaxation no longer reduces the residual: its rounding noise
-        // is the floor.  Gauss-Seidel sweeps (relaxation 1) damp that noise.
-        c->phase = 1;
-        c->relax = 1.0;
-        c->best = r;
-        c->best_at = c->sweeps;
-        c->polish_left = kPolishChecks;
-      }
-    } else if (--c->polish_left <= 0) {
-      st = SOLVE_FLOOR;
-      c->floor_limited = 1;
-    }
-    if (st == SOLVE_RUN && c->sweeps >= c->max_sweeps) st = SOLVE_NOCONV;
-  }
-  if (st != SOLVE_RUN) {
-    c->total_solves += 1;
-    if (st == SOLVE_FLOOR) c->total_floor += 1;
-    if (st == SOLVE_NOCONV) c->total_noconv += 1;
-    if (st == SOLVE_NONFINITE) c->total_nonfinite += 1;
-  }
-  c->state = st;
-}
 
 // ---------------------------------------------------------------------------
 // Temporally blocked four-colour relaxation of eq. (SequationFinal).
@@ -830,6 +779,58 @@ __global__ __launch_bounds__(NT) void k_sor(const T* __restrict__ pin, T* __rest
   }
 }
 
+// The decision of a Poisson solve after one residual check (see PoissonCtl).
+// r is max |g - psi| in the units of the relaxation formula.
+__device__ void decide(PoissonCtl* c, double r, double pm, long long sweeps_done) {
+  c->sweeps += sweeps_done;
+  c->total_sweeps += sweeps_done;
+  c->last = r;
+  c->psimax = pm;
+  // an opening of Gauss-Seidel sweeps ends at the first check after a sweep
+  if (c->gs_open && c->sweeps > 0) {
+    c->gs_open = 0;
+    c->relax = c->relax_sor;
+  }
+  int st = SOLVE_RUN;
+  if (!(r <= DBL_MAX)) {
+    st = SOLVE_NONFINITE;
+  } else if (r <= c->tol_hat) {
+    st = SOLVE_CONVERGED;
+  } else if (c->floor_ulps > 0.0 && r <= c->floor_ulps * DBL_EPSILON * pm) {
+    // The residual is at the rounding level of psi itself: no iteration can
+    // lower it further (multigrid reaches it in a few cycles).
+    st = SOLVE_FLOOR;
+    c->floor_limited = 1;
+  } else {
+    if (r < 0.5 * c->best) {
+      c->best = r;
+      c->best_at = c->sweeps;
+    }
+    if (c->phase == 0) {
+      if (c->sweeps - c->best_at >= c->stall_window) {
+        // Over-relaxation no longer reduces the residual: its rounding noise
+        // is the floor.  Gauss-Seidel sweeps (relaxation 1) damp that noise.
+        c->phase = 1;
+        c->relax = 1.0;
+        c->best = r;
+        c->best_at = c->sweeps;
+        c->polish_left = kPolishChecks;
+      }
+    } else if (--c->polish_left <= 0) {
+      st = SOLVE_FLOOR;
+      c->floor_limited = 1;
+    }
+    if (st == SOLVE_RUN && c->sweeps >= c->max_sweeps) st = SOLVE_NOCONV;
+  }
+  if (st != SOLVE_RUN) {
+    c->total_solves += 1;
+    if (st == SOLVE_FLOOR) c->total_floor += 1;
+    if (st == SOLVE_NOCONV) c->total_noconv += 1;
+    if (st == SOLVE_NONFINITE) c->total_nonfinite += 1;
+  }
+  c->state = st;
+}
+
 // The decision after a checking launch of nb blocks (one block).  A solve
 // that had already stopped launched no sweep, and its partial maxima are
 // stale: it is left alone.
@@ -1103,13 +1104,17 @@ __global__ __launch_bounds__(NT) void k_batch_mixed(const BatchMember* __restric
       batch_end(bc, gen);
       return;
     }
-    // FP32 correction sweeps; the last pair relaxes with 1.
+    // FP32 correction sweeps; the last pair relaxes with 1, the first with the
+    // control block's parameter (1 during a Gauss-Seidel opening), the others
+    // over-relax.
     for (int r = 0; r < 2 * inner_pairs; ++r) {
       const bool fwd = (r & 1) == 0;
       for (int t = blockIdx.x; t < total_tiles; t += nb) {
         const BatchMember& m = mem[member_of(mem, count, t)];
         if (load_state(m.ctl) != SOLVE_RUN) continue;
-        const float w = (r >= 2 * (inner_pairs - 1)) ? 1.0f : (float)m.ctl->relax;
+        const float w = (r >= 2 * (inner_pairs - 1)) ? 1.0f
+                        : (r < 2)                    ? (float)m.ctl->relax
+                                                     : (float)m.ctl->relax_sor;
         double rm = 0.0, pm = 0.0;
         sor_tile<float, TX, TY, S, NT, 0>(fwd ? m.d32a : m.d32b, fwd ? m.d32b : m.d32a, m.R32,
                                           m.n, m.pitch, t - m.tile0, m.tiles_x, w, sp, false, rm,

@@ -581,8 +581,10 @@ long long unit_sweeps(const Member& m);
 // w - 1 per sweep, Gauss-Seidel by a large factor.  Measured with the
 // oracle's four-colour sweep on those starts: 350 sweeps to 1e-10, 130 with
 // 10 Gauss-Seidel sweeps first, 90 with 20, 80 with 40.
+// In mixed precision the opening is the first pair of FP32 correction sweeps
+// of the solve's first refinement round.
 bool gs_opening(const Member& m) {
-  return m.warm >= 2 && !m.mixed && m.solver == CAVITY_SOLVER_SOR && m.fixed == 0;
+  return m.warm >= 2 && m.solver == CAVITY_SOLVER_SOR && m.fixed == 0;
 }
 
 // stage_solve: the solve of an SSPRK stage (its start may be an extrapolation).
@@ -708,8 +710,10 @@ int enqueue_chunk(cavity_s* h, Member& m, int units) {
       const int pairs = m.inner_sweeps / (2 * m.cfg32.s);
       for (int q = 0; q < pairs; ++q) {
         // the last pair relaxes with 1 (Gauss-Seidel) to damp the FP32
-        // over-relaxation noise before the correction is applied
-        const double rl = (q == pairs - 1) ? 1.0 : m.relax;
+        // over-relaxation noise before the correction is applied; the first
+        // takes the control block's parameter (1 during a Gauss-Seidel
+        // opening or after a stall, else m.relax)
+        const double rl = (q == pairs - 1) ? 1.0 : (q == 0 ? 0.0 : m.relax);
         HIP_TRY(h, cav::launch_sor32(m.cfg32, m.d32a, m.d32b, m.R32, m.n, m.pitch, m.ctl, rl,
                                      h->st));
         HIP_TRY(h, cav::launch_sor32(m.cfg32, m.d32b, m.d32a, m.R32, m.n, m.pitch, m.ctl, rl,
@@ -1008,7 +1012,7 @@ int enqueue_batch_solve(cavity_s* h) {
     const double tol_hat = m.tol * 0.3 * m.h * m.h;
     HIP_TRY(h, cav::launch_ctl_reset(m.ctl, m.relax, tol_hat, m.max_sweeps, m.stall_window,
                                      batch_check_sweeps(h), h->st, 0.0,
-                                     !h->mixed && gs_opening(m) ? m.warm_cnt : nullptr));
+                                     gs_opening(m) ? m.warm_cnt : nullptr));
     if (!h->mixed)
       HIP_TRY(h, cav::launch_resid64(m.psi, m.F, nullptr, nullptr, m.n, m.pitch, m.ctl, m.part,
                                      h->st));
