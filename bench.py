@@ -45,8 +45,8 @@ EXEC = {"stream": 0, "persistent": 1, "graph": 2, "resident": 3}
 
 def _kernel_source_hash() -> str:
     """Hash of the code a sweep launch runs: the kernel source up to the end
-    of the sweep kernel's definition (everything it can refer to) and its
-    tile-configuration dispatch, with comments, blank lines and trailing
+    of the sweep kernel's definition (everything it can refer to) and the
+    host function that launches it, with comments, blank lines and trailing
     blanks left out, so that only a change to that code invalidates the
     recorded counters (the file has no string literal holding a comment
     marker)."""
@@ -56,7 +56,7 @@ def _kernel_source_hash() -> str:
     k = next(i for i, ln in enumerate(lines) if "void k_sor(" in ln)
     end_a = next(i for i in range(k, len(lines)) if lines[i] == "}")
     b = next(i for i, ln in enumerate(lines) if ln.startswith("hipError_t sor_launch(")) - 1
-    end_b = next(i for i in range(b, len(lines)) if lines[i].startswith("}  // namespace"))
+    end_b = next(i for i in range(b, len(lines)) if lines[i] == "}")
     text = "\n".join(lines[:end_a + 1] + lines[b:end_b + 1])
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     code = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
