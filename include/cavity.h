@@ -87,7 +87,7 @@ enum cavity_precision {
 enum cavity_warm_start {
   CAVITY_WARM_DEFAULT = 0,
   CAVITY_WARM_PREVIOUS = 1,
-  CAVITY_WARM_LEVELS_FP64 = 7,
+  CAVITY_WARM_LEVELS_FP64 = 6,
   CAVITY_WARM_LEVELS_MIXED = 8,
   CAVITY_WARM_DEGREE_MIXED = 5,
   CAVITY_WARM_LEVELS_MAX = 8

@@ -41,7 +41,7 @@ CAVITY_SOLVER_SOR = 0
 CAVITY_SOLVER_MG = 1
 CAVITY_WARM_DEFAULT = 0
 CAVITY_WARM_PREVIOUS = 1
-CAVITY_WARM_LEVELS_FP64 = 7
+CAVITY_WARM_LEVELS_FP64 = 6
 CAVITY_WARM_LEVELS_MIXED = 8
 CAVITY_WARM_DEGREE_MIXED = 5
 CAVITY_WARM_LEVELS_MAX = 8
