@@ -166,9 +166,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed and batched lines")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated subset of the extra lines: multigrid, persistent, "
+                    help="comma-separated subset of the extra lines: multigrid, mixed_head, "
+                         "persistent, "
                          "resident, re3e4, n4096, coupled, re_sweep6_fp64, re_sweep6_mixed, "
                          "re_scan16_small_fp64 (default all)")
+    ap.add_argument("--poisson-tol", type=float, default=None,
+                    help="Poisson tolerance of the headline run (default: the workload's)")
     ap.add_argument("--solver", default="sor", choices=["sor", "multigrid"],
                     help="Poisson solver of the headline workload")
     ap.add_argument("--set-tuning", default="", metavar="KEY=VALUE,...",
@@ -315,7 +318,7 @@ def main():
                 cav.close()
         return
 
-    def single(name, steps, warmup, mode, solver=0, precision=None, tuning=None):
+    def single(name, steps, warmup, mode, solver=0, precision=None, tuning=None, tol=None):
         wl = WORKLOADS[name]
         prec = CAVITY_MIXED if wl["precision"] == "mixed" else CAVITY_FP64
         if precision is not None:
@@ -323,7 +326,7 @@ def main():
         omega0 = None
         if wl["init"] == "noise":
             omega0 = [inputs.noise_omega0(wl["n"], wl["noise_amplitude"], wl["noise_seed"])]
-        cav = Cavity(Params(n=wl["n"], re=wl["re"], poisson_tol=wl["tol"], precision=prec,
+        cav = Cavity(Params(n=wl["n"], re=wl["re"], poisson_tol=tol or wl["tol"], precision=prec,
                             warm_start=args.warm_start),
                      device="cuda:0", stream=stream, omega0=omega0)
         if solver:
@@ -352,7 +355,8 @@ def main():
         head_tuning[key] = float(val) if key == "sor_omega" else int(val)
     cav, prec, head = single(args.workload, args.steps, args.warmup, args.exec,
                              CAVITY_SOLVER_MG if args.solver == "multigrid" else 0,
-                             precision=prec_override, tuning=head_tuning)
+                             precision=prec_override, tuning=head_tuning,
+                             tol=args.poisson_tol)
     wl = WORKLOADS[args.workload]
     n = wl["n"]
     roofline = _sweep_roofline(torch, cav, stream, args.relax_launches, 0,
@@ -364,8 +368,8 @@ def main():
 
     extras = {}
     chosen = set() if args.no_extras else (
-        {"multigrid", "persistent", "resident", "re3e4", "n4096", "coupled", "re_sweep6_fp64",
-         "re_sweep6_mixed", "re_scan16_small_fp64"} if args.extras == "all"
+        {"multigrid", "mixed_head", "persistent", "resident", "re3e4", "n4096", "coupled",
+         "re_sweep6_fp64", "re_sweep6_mixed", "re_scan16_small_fp64"} if args.extras == "all"
         else set(args.extras.split(",")))
     if "multigrid" in chosen:
         # same workload, multigrid solver (same compact equation, same tolerance)
@@ -373,6 +377,18 @@ def main():
         mg["vcycles_per_stage"] = mg["sweeps_per_stage"] / 4 if mg["sweeps_per_stage"] else None
         cmg.close()
         extras["multigrid_1024_re1e4_fp64"] = mg
+    if "mixed_head" in chosen and prec != CAVITY_MIXED:
+        # mixed + refinement on the headline workload itself, same steps and warm-up.  Its
+        # solves stop at the first FP64 residual check (taken after a Gauss-Seidel pair)
+        # below the tolerance; the FP64 solves read the residual right after over-relaxed
+        # sweeps, which at 1024^2 stays above 1e-10 until it drops within one check
+        # interval to 30-70 times below it (1.5e-12 at the stops after 100 steps, 3e-12
+        # late in the run)
+        cmh, _, mh = single(args.workload, args.steps, args.warmup, args.exec,
+                            precision=CAVITY_MIXED)
+        cmh.close()
+        mh["speedup_vs_fp64_same_workload"] = round(mh["value"] / head["value"], 3)
+        extras["mixed_1024_re1e4"] = mh
     if "persistent" in chosen:
         # the persistent-kernel and resident-solve executions of the headline workload
         cp, _, pers = single(args.workload, args.extra_steps, 1, "persistent")
@@ -484,7 +500,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == CAVITY_FP64 else "f32+f64", "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "re": wl["re"], "poisson_tol": wl["tol"],
+        "config": {"workload": args.workload, "n": n, "re": wl["re"], "poisson_tol": args.poisson_tol or wl["tol"],
                    "precision": head["precision"], "solver": head["solver"], "init": wl["init"],
                    "exec": head["exec"],
                    "sweeps_per_stage": head["sweeps_per_stage"],
