@@ -416,6 +416,17 @@ int cavity_autotune(cavity_t h, int32_t idx, const char* cache_path, cavity_tuni
 /* Release the handle (host memory only; the workspace stays the caller's). */
 int cavity_destroy(cavity_t h);
 
+/* The weights of the warm start of a stage solve (see enum cavity_warm_start;
+ * Sec. 3, eqs. SSPRK54_1-5 with eq. SequationFinal per stage): with `levels`
+ * steps on file, the start is sum_q w[q-1] psi(step - q), q = 1 ... levels,
+ * the value at the current step of the polynomial of the given degree through
+ * the same stage's solutions of those steps (interpolation for degree =
+ * levels - 1, least squares below).  The same weights the device applies.
+ * Host only (no device, no handle); w (host) receives `levels` doubles.
+ * CAVITY_EINVAL for levels outside [2, CAVITY_WARM_LEVELS_MAX], degree
+ * outside [1, levels - 1] or w NULL. */
+int cavity_warm_weights(int32_t levels, int32_t degree, double* w);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* cavity_last_error(void);
 

@@ -131,18 +131,27 @@ _lib.cavity_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_
 _lib.cavity_set_exec.argtypes = [ctypes.c_void_p, ctypes.c_int32]
 _lib.cavity_get_exec.argtypes = [ctypes.c_void_p, _P(ctypes.c_int32)]
 _lib.cavity_destroy.argtypes = [ctypes.c_void_p]
+_lib.cavity_warm_weights.argtypes = [ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double)]
 _lib.cavity_last_error.restype = ctypes.c_char_p
 for _f in ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_run_steady",
            "cavity_poisson", "cavity_poisson_noalloc",
            "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
-           "cavity_set_exec", "cavity_get_exec", "cavity_autotune", "cavity_destroy"):
+           "cavity_set_exec", "cavity_get_exec", "cavity_autotune", "cavity_destroy",
+           "cavity_warm_weights"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("cavity_workspace_bytes", "cavity_create", "cavity_step", "cavity_run_steady",
             "cavity_poisson", "cavity_poisson_noalloc",
             "cavity_fields", "cavity_relax", "cavity_get_tuning", "cavity_set_tuning",
             "cavity_set_exec", "cavity_get_exec", "cavity_autotune", "cavity_destroy",
-            "cavity_last_error")
+            "cavity_warm_weights", "cavity_last_error")
+
+
+def cavity_warm_weights(levels: int, degree: int) -> np.ndarray:
+    """Warm-start weights w[q-1] of psi(step - q), q = 1 ... levels (host only)."""
+    w = (ctypes.c_double * max(levels, 1))()
+    _check(_lib.cavity_warm_weights(levels, degree, w))
+    return np.array(w[:levels], dtype=np.float64)
 
 
 def cavity_last_error() -> str:

@@ -1531,6 +1531,16 @@ extern "C" {
 
 const char* cavity_last_error(void) { return g_err.c_str(); }
 
+int cavity_warm_weights(int32_t levels, int32_t degree, double* w) {
+  if (!w) return fail(CAVITY_EINVAL, "null argument");
+  if (levels < 2 || levels > CAVITY_WARM_LEVELS_MAX)
+    return fail(CAVITY_EINVAL, "levels = %d outside [2, %d]", levels, CAVITY_WARM_LEVELS_MAX);
+  if (degree < 1 || degree > levels - 1)
+    return fail(CAVITY_EINVAL, "degree = %d outside [1, %d]", degree, levels - 1);
+  warm_weights(levels, degree, w);
+  return CAVITY_OK;
+}
+
 int cavity_workspace_bytes(const cavity_params* p, int32_t count, size_t* bytes) {
   if (!p || !bytes) return fail(CAVITY_EINVAL, "null argument");
   if (count < 1) return fail(CAVITY_EINVAL, "count must be >= 1");
