@@ -14,6 +14,10 @@ from dataclasses import dataclass, field
 from typing import Optional, Sequence
 
 import numpy as np
+# torch first: its HIP runtime is then the one the library binds to, the order
+# in which the two are used together (the library loaded before torch has had
+# torch run on the other runtime build and pinned host allocations fail)
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcavity.so")

@@ -9,26 +9,40 @@ the interpolating weights are the alternating binomials (Lagrange weights at
 property (numpy's SVD-based lstsq of the underdetermined system), which is
 what evaluating a least-squares fit amounts to."""
 import math
+import os
+import re
 
 import numpy as np
 import pytest
 
-from paper_0809_3098_amd import cavity as cav
+# The largest number of levels, read from the header: the library itself is
+# loaded only by the fixture below, so that collecting this module (also in a
+# GPU run, which deselects it) does not load the HIP runtime before torch.
+_HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "include", "cavity.h")
+LEVELS_MAX = int(re.search(r"CAVITY_WARM_LEVELS_MAX\s*=\s*(\d+)", open(_HEADER).read()).group(1))
 
 
-@pytest.mark.parametrize("levels", range(2, cav.CAVITY_WARM_LEVELS_MAX + 1))
-def test_interpolating_weights_are_alternating_binomials(levels):
+@pytest.fixture(scope="module")
+def cav():
+    from paper_0809_3098_amd import cavity
+    assert cavity.CAVITY_WARM_LEVELS_MAX == LEVELS_MAX
+    return cavity
+
+
+@pytest.mark.parametrize("levels", range(2, LEVELS_MAX + 1))
+def test_interpolating_weights_are_alternating_binomials(cav, levels):
     w = cav.cavity_warm_weights(levels, levels - 1)
     expect = [(-1) ** (q + 1) * math.comb(levels, q) for q in range(1, levels + 1)]
     assert w.tolist() == [float(e) for e in expect]
 
 
 def _all_cases():
-    return [(L, d) for L in range(2, cav.CAVITY_WARM_LEVELS_MAX + 1) for d in range(1, L)]
+    return [(L, d) for L in range(2, LEVELS_MAX + 1) for d in range(1, L)]
 
 
 @pytest.mark.parametrize("levels,degree", _all_cases())
-def test_weights_reproduce_polynomials_of_their_degree(levels, degree):
+def test_weights_reproduce_polynomials_of_their_degree(cav, levels, degree):
     w = cav.cavity_warm_weights(levels, degree)
     q = np.arange(1, levels + 1, dtype=np.float64)
     rng = np.random.default_rng(1000 * levels + degree)
@@ -43,7 +57,7 @@ def test_weights_reproduce_polynomials_of_their_degree(levels, degree):
 
 
 @pytest.mark.parametrize("levels,degree", [c for c in _all_cases() if c[1] < c[0] - 1])
-def test_least_squares_weights_are_the_minimum_norm_exact_weights(levels, degree):
+def test_least_squares_weights_are_the_minimum_norm_exact_weights(cav, levels, degree):
     w = cav.cavity_warm_weights(levels, degree)
     q = np.arange(1, levels + 1, dtype=np.float64)
     # constraints sum_q w_q (-q)^k = delta_k0, k = 0 ... degree, in a scaled
@@ -56,7 +70,7 @@ def test_least_squares_weights_are_the_minimum_norm_exact_weights(levels, degree
     assert np.max(np.abs(w - w_min)) <= 1e-12 * np.max(np.abs(w_min)), (w, w_min)
 
 
-def test_noise_gain_of_the_default_fits():
+def test_noise_gain_of_the_default_fits(cav):
     """sqrt(sum w^2), the factor by which the fit passes on independent
     tolerance-level differences of the solutions on file."""
     gain = lambda L, d: float(np.sqrt(np.sum(cav.cavity_warm_weights(L, d) ** 2)))
@@ -67,8 +81,7 @@ def test_noise_gain_of_the_default_fits():
     assert gain(8, 5) < gain(8, 7)
 
 
-@pytest.mark.parametrize("levels,degree", [(1, 1), (cav.CAVITY_WARM_LEVELS_MAX + 1, 2),
-                                           (5, 0), (5, 5)])
-def test_out_of_range_levels_and_degrees_are_rejected(levels, degree):
+@pytest.mark.parametrize("levels,degree", [(1, 1), (LEVELS_MAX + 1, 2), (5, 0), (5, 5)])
+def test_out_of_range_levels_and_degrees_are_rejected(cav, levels, degree):
     with pytest.raises(cav.CavityError):
         cav.cavity_warm_weights(levels, degree)
