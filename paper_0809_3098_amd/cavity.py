@@ -14,9 +14,10 @@ from dataclasses import dataclass, field
 from typing import Optional, Sequence
 
 import numpy as np
-# torch first: its HIP runtime is then the one the library binds to, the order
-# in which the two are used together (the library loaded before torch has had
-# torch run on the other runtime build and pinned host allocations fail)
+# torch first: the library then binds to the HIP runtime torch has loaded.
+# Loaded before torch, the library binds to the system's HIP runtime and torch
+# loads its own, two runtimes in one process, and the library's pinned host
+# allocations fail.
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
