@@ -29,7 +29,7 @@ index, fastest), y_j = j*h (row index), h = 1/(n-1); walls at i or j equal to
 0 and n-1; the moving lid is the top row j = n-1 (Sec. 3, driven-cavity
 figure and boundary conditions).
 
-Readings of the paper taken here (each is also listed in the design doc):
+Readings of the paper taken here:
 
 * alpha_21 is printed as 0.555626506348765, which makes the stage-2
   coefficients sum to 0.999997; a Shu-Osher stage must be a convex combination
